@@ -1,0 +1,305 @@
+/*
+ * CPU FP64 oracle for the 1D x 1D Vlasov-Poisson split step.
+ *
+ * TEST INFRASTRUCTURE ONLY: called by the tests, by the smoke check and by
+ * the benchmark's CPU-baseline leg, never by the product library.
+ *
+ * What it computes, and where the paper defines it:
+ *   - Strang splitting v(dt/2) -> x(dt) -> field update -> v(dt/2)
+ *     (Section 1.1, steps 1-3; the last half step is not merged with the
+ *     next step's first one).
+ *   - Each constant advection u_i <- pi u(x_i - c dt) as the circulant
+ *     product A u with A = C(a_0 .. a_{N-1}) (Section 1.2, eq. of matrix A),
+ *     beta = -c dt / dx = b + s with b integer and s in [0, 1), and the
+ *     Lagrange 2d+1 coefficients a_{b+j} = prod_{k != j} (s - k) / (j - k),
+ *     j = -d .. d+1.  Here the product is evaluated directly, as the sum over
+ *     the 2d+2 nonzero entries of each row; no FFT is used.
+ *   - The delta-f v-advection (Section 3.1): the advected perturbation plus
+ *     f_eq(v - tau E) - f_eq(v), f_eq evaluated, not interpolated.
+ *   - rho_i = dv sum_j f_ij (rectangle rule on the periodic v grid) and the
+ *     Fourier Poisson solve with mode 0 set to zero (Section 3.2), which
+ *     gives a zero-mean E.  The Nyquist mode is also set to zero.
+ *   - Diagnostics of Section 4: ||E||_2, the mass rho_hat_0, |rho_hat_1|,
+ *     the L2 norm of f and the total energy.
+ */
+#include "vp_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+static const double ORC_PI = 3.14159265358979323846264338327950288;
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+static long wrap(long i, long n) {
+    long r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+/* Lagrange 2d+1 coefficients (Section 1.2): w[j + d] for j = -d .. d+1. */
+void orc_lagrange_weights(int d, double s, double *w) {
+    for (int j = -d; j <= d + 1; ++j) {
+        double p = 1.0;
+        for (int k = -d; k <= d + 1; ++k)
+            if (k != j) p *= (s - (double)k) / (double)(j - k);
+        w[j + d] = p;
+    }
+}
+
+/* beta = b + s with b integer and s in [0, 1) (Section 1.2). */
+void orc_split_shift(double beta, long *b, double *s) {
+    double fb = floor(beta);
+    double r = beta - fb;
+    if (r >= 1.0) { /* beta - floor(beta) rounded up to 1 */
+        r = 0.0;
+        fb += 1.0;
+    }
+    *b = (long)fb;
+    *s = r;
+}
+
+/* First row a_0 .. a_{n-1} of the circulant matrix A (Section 1.2):
+ * a_{(b+j) mod n} = w_j, all other entries zero. */
+void orc_circulant_row(int n, int d, double beta, double *a) {
+    long b;
+    double s;
+    double w[64];
+    orc_split_shift(beta, &b, &s);
+    orc_lagrange_weights(d, s, w);
+    for (int k = 0; k < n; ++k) a[k] = 0.0;
+    for (int j = -d; j <= d + 1; ++j) a[wrap(b + j, n)] += w[j + d];
+}
+
+/* out = A u for one line: out_i = sum_k A_{ik} u_k = sum_j w_j u_{(i+b+j) mod n}. */
+static void advect_strided(int n, int d, long b, const double *w,
+                           const double *u, long us, double *out, long os) {
+    for (long i = 0; i < n; ++i) {
+        double acc = 0.0;
+        for (int j = -d; j <= d + 1; ++j) acc += w[j + d] * u[wrap(i + b + j, n) * us];
+        out[i * os] = acc;
+    }
+}
+
+void orc_advect_line(int n, int d, double beta, const double *u, double *out) {
+    long b;
+    double s;
+    double w[64];
+    orc_split_shift(beta, &b, &s);
+    orc_lagrange_weights(d, s, w);
+    advect_strided(n, d, b, w, u, 1, out, 1);
+}
+
+static double dx_of(const orc_cfg *c) { return c->L / c->nx; }
+static double dv_of(const orc_cfg *c) { return (c->vmax - c->vmin) / c->nv; }
+static double v_of(const orc_cfg *c, int j) { return c->vmin + j * dv_of(c); }
+static double x_of(const orc_cfg *c, int i) { return i * dx_of(c); }
+
+/* f_eq(v) = sum_g a_g exp(-(v - c_g)^2 / (2 sigma_g^2)); the unit Maxwellian of
+ * Section 3.1 is one term with a = 1/sqrt(2 pi), c = 0, sigma = 1. */
+double orc_feq(const orc_cfg *c, double v) {
+    double acc = 0.0;
+    for (int g = 0; g < c->n_feq; ++g) {
+        double z = (v - c->feq_c[g]) / c->feq_sigma[g];
+        acc += c->feq_a[g] * exp(-0.5 * z * z);
+    }
+    return acc;
+}
+
+/* f0 = (1 + sum_m amp_m cos(kx_m x + phase_m)) f_eq(v); delta f stores f0 - f_eq. */
+void orc_init(const orc_cfg *c, int nmodes, const double *amp, const double *kx,
+              const double *phase, double *f) {
+    for (int i = 0; i < c->nx; ++i) {
+        double p = 0.0;
+        for (int m = 0; m < nmodes; ++m) p += amp[m] * cos(kx[m] * x_of(c, i) + phase[m]);
+        for (int j = 0; j < c->nv; ++j) {
+            double fe = orc_feq(c, v_of(c, j));
+            f[(long)i * c->nv + j] = c->deltaf ? p * fe : (1.0 + p) * fe;
+        }
+    }
+}
+
+/* x-advection by dt (Section 1.1, step 2): for each v_j, c = v_j. */
+void orc_advect_x(const orc_cfg *c, double dt, const double *f, double *out) {
+    const int d = (c->degree - 1) / 2;
+    const double dx = dx_of(c);
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < c->nv; ++j) {
+        long b;
+        double s;
+        double w[64];
+        orc_split_shift(-v_of(c, j) * dt / dx, &b, &s);
+        orc_lagrange_weights(d, s, w);
+        advect_strided(c->nx, d, b, w, f + j, c->nv, out + j, c->nv);
+    }
+}
+
+/* v-advection by tau with field E (Section 1.1, steps 1 and 3; delta f form of
+ * Section 3.1): for each x_i, c = E_i. */
+void orc_advect_v(const orc_cfg *c, const double *E, double tau, const double *f, double *out) {
+    const int d = (c->degree - 1) / 2;
+    const double dv = dv_of(c);
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < c->nx; ++i) {
+        long b;
+        double s;
+        double w[64];
+        const double Ei = c->field_zero ? 0.0 : E[i];
+        orc_split_shift(-Ei * tau / dv, &b, &s);
+        orc_lagrange_weights(d, s, w);
+        const double *u = f + (long)i * c->nv;
+        double *o = out + (long)i * c->nv;
+        advect_strided(c->nv, d, b, w, u, 1, o, 1);
+        if (c->deltaf) {
+            for (int j = 0; j < c->nv; ++j) {
+                double v = v_of(c, j);
+                o[j] += orc_feq(c, v - tau * Ei) - orc_feq(c, v);
+            }
+        }
+    }
+}
+
+/* rho_i = int f dv by the rectangle rule; delta f adds the f_eq integral. */
+void orc_rho(const orc_cfg *c, const double *f, double *rho) {
+    const double dv = dv_of(c);
+    double feq_sum = 0.0;
+    if (c->deltaf)
+        for (int j = 0; j < c->nv; ++j) feq_sum += orc_feq(c, v_of(c, j));
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < c->nx; ++i) {
+        double acc = 0.0;
+        for (int j = 0; j < c->nv; ++j) acc += f[(long)i * c->nv + j];
+        rho[i] = dv * (acc + feq_sum);
+    }
+}
+
+/* Fourier Poisson solve dE/dx = rho - mean(rho) by direct DFT (Section 3.2):
+ * rho_hat_m = sum_i rho_i e^{-2 pi i m i / nx}; E_hat_0 = E_hat_{nx/2} = 0,
+ * E_hat_m = rho_hat_m / (i k_m), k_m = 2 pi mt / L with mt the signed index;
+ * E_i = Re (1/nx) sum_m E_hat_m e^{+2 pi i m i / nx}. */
+void orc_poisson(const orc_cfg *c, const double *rho, double *E) {
+    const int n = c->nx;
+    double *cs = (double *)malloc(sizeof(double) * 2 * n);
+    double *sn = cs + n;
+    double *Er = (double *)malloc(sizeof(double) * 2 * n);
+    double *Ei = Er + n;
+    for (int k = 0; k < n; ++k) {
+        cs[k] = cos(2.0 * ORC_PI * k / n);
+        sn[k] = sin(2.0 * ORC_PI * k / n);
+    }
+#pragma omp parallel for schedule(static)
+    for (int m = 0; m < n; ++m) {
+        double re = 0.0, im = 0.0;
+        for (int i = 0; i < n; ++i) {
+            long k = ((long)m * i) % n;
+            re += rho[i] * cs[k];
+            im -= rho[i] * sn[k];
+        }
+        if (m == 0 || 2 * m == n) {
+            Er[m] = 0.0;
+            Ei[m] = 0.0;
+        } else {
+            int mt = (2 * m < n) ? m : m - n;
+            double km = 2.0 * ORC_PI * mt / c->L;
+            /* (re + i im) / (i km) = (im - i re) / km */
+            Er[m] = im / km;
+            Ei[m] = -re / km;
+        }
+    }
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < n; ++i) {
+        double acc = 0.0;
+        for (int m = 0; m < n; ++m) {
+            long k = ((long)m * i) % n;
+            acc += Er[m] * cs[k] - Ei[m] * sn[k];
+        }
+        E[i] = acc / n;
+    }
+    free(cs);
+    free(Er);
+}
+
+void orc_field(const orc_cfg *c, const double *f, double *E, double *rho) {
+    orc_rho(c, f, rho);
+    if (c->field_zero)
+        for (int i = 0; i < c->nx; ++i) E[i] = 0.0;
+    else
+        orc_poisson(c, rho, E);
+}
+
+/* One Strang step (Section 1.1).  f, E hold f^n, E^n on entry and f^{n+1},
+ * E^{n+1} on exit; rho receives the density the new field was solved from;
+ * tmp has nx*nv doubles. */
+void orc_step(const orc_cfg *c, double dt, double *f, double *E, double *rho, double *tmp) {
+    const long cells = (long)c->nx * c->nv;
+    orc_advect_v(c, E, 0.5 * dt, f, tmp);
+    orc_advect_x(c, dt, tmp, f);
+    orc_field(c, f, E, rho);
+    orc_advect_v(c, E, 0.5 * dt, f, tmp);
+    memcpy(f, tmp, sizeof(double) * cells);
+}
+
+/* ||E||_2 = (dx sum E^2)^{1/2}; rho_hat_0 = mean rho; |rho_hat_1| with
+ * rho_hat_m = (1/nx) sum_i rho_i e^{-2 pi i m i / nx}. */
+void orc_diag_field(const orc_cfg *c, const double *rho, const double *E, double *out3) {
+    const int n = c->nx;
+    double e2 = 0.0, r0 = 0.0, r1r = 0.0, r1i = 0.0;
+    for (int i = 0; i < n; ++i) {
+        e2 += E[i] * E[i];
+        r0 += rho[i];
+        r1r += rho[i] * cos(2.0 * ORC_PI * i / n);
+        r1i -= rho[i] * sin(2.0 * ORC_PI * i / n);
+    }
+    out3[0] = sqrt(dx_of(c) * e2);
+    out3[1] = r0 / n;
+    out3[2] = sqrt(r1r * r1r + r1i * r1i) / n;
+}
+
+/* L2 = dx dv sum f^2 and total energy = dx dv sum f v^2 / 2 + dx/2 sum E^2
+ * (Section 4.2), with f the full distribution (f_eq added back for delta f). */
+void orc_diag_moments(const orc_cfg *c, const double *f, const double *E, double *out2) {
+    const double dx = dx_of(c), dv = dv_of(c);
+    double l2 = 0.0, ek = 0.0, ee = 0.0;
+    for (int i = 0; i < c->nx; ++i) {
+        for (int j = 0; j < c->nv; ++j) {
+            double v = v_of(c, j);
+            double fij = f[(long)i * c->nv + j] + (c->deltaf ? orc_feq(c, v) : 0.0);
+            l2 += fij * fij;
+            ek += fij * v * v;
+        }
+        ee += E[i] * E[i];
+    }
+    out2[0] = dx * dv * l2;
+    out2[1] = 0.5 * dx * dv * ek + 0.5 * dx * ee;
+}
+
+/* nsteps Strang steps; diag (3 doubles per step, may be NULL) receives
+ * ||E^{n+1}||_2, rho_hat_0 and |rho_hat_1| after each step. */
+void orc_run(const orc_cfg *c, double dt, int nsteps, double *f, double *E, double *diag) {
+    const long cells = (long)c->nx * c->nv;
+    double *tmp = (double *)malloc(sizeof(double) * cells);
+    double *rho = (double *)malloc(sizeof(double) * c->nx);
+    for (int n = 0; n < nsteps; ++n) {
+        orc_step(c, dt, f, E, rho, tmp);
+        if (diag) orc_diag_field(c, rho, E, diag + 3L * n);
+    }
+    free(tmp);
+    free(rho);
+}

@@ -1,0 +1,64 @@
+/*
+ * CPU FP64 oracle for the 1D x 1D Vlasov-Poisson split step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library exists so that tests, the smoke
+ * check and the CPU-baseline timing can check the HIP library against a
+ * plain, slow, obviously correct computation.  The product path never links,
+ * loads or calls it.  It shares no code, header, table or constant with the
+ * HIP library.
+ *
+ * Every advection is the direct circulant stencil of the paper's Lagrange
+ * 2d+1 interpolation (Section 1.2): no FFT is used anywhere.  The Poisson
+ * solve is a direct O(Nx^2) DFT with mode 0 (and the Nyquist mode) set to
+ * zero (Section 3.2, Fourier variant).
+ *
+ * Layout of f: f[ix * nv + jv], v fastest.  x_i = i L / nx for i < nx,
+ * v_j = vmin + j (vmax - vmin) / nv for j < nv (both periodic).
+ */
+#ifndef VP_ORACLE_H
+#define VP_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_MAX_FEQ 4
+
+typedef struct {
+    int nx, nv;
+    double L, vmin, vmax;
+    int degree;        /* odd, 2d+1 */
+    int deltaf;        /* 0: f is stored and advected; 1: delta f = f - f_eq */
+    int field_zero;    /* 1: E is held at zero (free streaming) */
+    int n_feq;
+    double feq_a[ORC_MAX_FEQ], feq_c[ORC_MAX_FEQ], feq_sigma[ORC_MAX_FEQ];
+} orc_cfg;
+
+int orc_num_threads(void);
+void orc_set_num_threads(int n);
+
+void orc_lagrange_weights(int d, double s, double *w);
+void orc_split_shift(double beta, long *b, double *s);
+void orc_circulant_row(int n, int d, double beta, double *a);
+void orc_advect_line(int n, int d, double beta, const double *u, double *out);
+
+double orc_feq(const orc_cfg *c, double v);
+void orc_init(const orc_cfg *c, int nmodes, const double *amp, const double *kx,
+              const double *phase, double *f);
+
+void orc_advect_x(const orc_cfg *c, double dt, const double *f, double *out);
+void orc_advect_v(const orc_cfg *c, const double *E, double tau, const double *f, double *out);
+void orc_rho(const orc_cfg *c, const double *f, double *rho);
+void orc_poisson(const orc_cfg *c, const double *rho, double *E);
+void orc_field(const orc_cfg *c, const double *f, double *E, double *rho);
+
+void orc_step(const orc_cfg *c, double dt, double *f, double *E, double *rho, double *tmp);
+void orc_run(const orc_cfg *c, double dt, int nsteps, double *f, double *E, double *diag);
+
+void orc_diag_field(const orc_cfg *c, const double *rho, const double *E, double *out3);
+void orc_diag_moments(const orc_cfg *c, const double *f, const double *E, double *out2);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,273 @@
+"""Pins of the CPU FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: algebraic
+identities of Lagrange interpolation, exact integer shifts, exact translation
+of resolved Fourier modes, closed-form Poisson solutions, the free-streaming
+exact solution, conservation laws, the paper's Landau damping rate and
+oscillation counts, and second-order convergence of the Strang splitting.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import workloads
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+RNG = np.random.default_rng(1234)
+
+
+# ------------------------------------------------------------------ weights
+
+@pytest.mark.parametrize("d", [0, 1, 4, 8])
+def test_weights_partition_of_unity(orc, d):
+    for s in RNG.uniform(0, 1, 20):
+        assert abs(orc.lagrange_weights(d, s).sum() - 1.0) < 1e-13
+
+
+@pytest.mark.parametrize("d", [1, 4, 8])
+def test_weights_reproduce_polynomials(orc, d):
+    # Lagrange interpolation on nodes -d..d+1 is exact for degree <= 2d+1:
+    # sum_q w_q(s) p(q) = p(s).
+    q = np.arange(-d, d + 2)
+    for s in RNG.uniform(0, 1, 10):
+        w = orc.lagrange_weights(d, s)
+        for k in range(2 * d + 2):
+            p = lambda x: ((x - 0.5) / (d + 1)) ** k
+            assert abs(np.dot(w, p(q)) - p(s)) < 1e-13
+
+
+@pytest.mark.parametrize("d", [1, 4, 8])
+def test_weights_not_exact_beyond_degree(orc, d):
+    # Degree 2d+2 is not reproduced (guards against a dropped node).
+    q = np.arange(-d, d + 2)
+    w = orc.lagrange_weights(d, 0.37)
+    p = lambda x: ((x - 0.5) / (d + 1)) ** (2 * d + 2)
+    assert abs(np.dot(w, p(q)) - p(0.37)) > 1e-10
+
+
+@pytest.mark.parametrize("d", [0, 1, 4, 8])
+def test_weights_mirror_symmetry(orc, d):
+    # w_q(s) = w_{1-q}(1-s): the stencil is centred on the cell of the foot.
+    for s in RNG.uniform(0, 1, 5):
+        w = orc.lagrange_weights(d, s)
+        wm = orc.lagrange_weights(d, 1.0 - s)
+        assert np.allclose(w, wm[::-1], rtol=0, atol=1e-14)
+
+
+def test_lagrange1_closed_form(orc):
+    # Section 1.2, Lagrange 1: a_b = 1 - b*, a_{b+1} = b*.
+    for s in RNG.uniform(0, 1, 10):
+        assert np.allclose(orc.lagrange_weights(0, s), [1.0 - s, s], atol=1e-15)
+
+
+@pytest.mark.parametrize("d", [0, 4, 8])
+def test_weights_at_zero_shift(orc, d):
+    w = orc.lagrange_weights(d, 0.0)
+    e = np.zeros(2 * d + 2)
+    e[d] = 1.0
+    assert np.array_equal(w, e)
+
+
+def test_split_shift(orc):
+    for beta in [0.0, 0.25, -0.25, 3.0, -3.0, 52.7, -52.7, 1e-17, -1e-17, 7.999999999]:
+        b, s = orc.split_shift(beta)
+        assert isinstance(b, int) and 0.0 <= s < 1.0
+        assert abs((b + s) - beta) <= 1e-15 * max(1.0, abs(beta))
+
+
+# ------------------------------------------------------------------ one line
+
+@pytest.mark.parametrize("beta", [0, 1, -1, 5, -17, 64, 131, -200])
+def test_integer_shift_is_exact_roll(orc, beta):
+    n = 64
+    u = RNG.standard_normal(n)
+    out = orc.advect_line(u, 8, float(beta))
+    # out_i = u_{(i + beta) mod n}
+    assert np.array_equal(out, np.roll(u, -beta))
+
+
+@pytest.mark.parametrize("beta", [0.3, 2.71, -4.45, -0.999])
+def test_polynomial_reproduction_interior(orc, beta):
+    d, n = 8, 128
+    coef = RNG.standard_normal(2 * d + 2)
+    p = lambda x: np.polyval(coef, (x - n / 2) / n)
+    i = np.arange(n)
+    out = orc.advect_line(p(i.astype(float)), d, beta)
+    b = math.floor(beta)
+    interior = (i + b - d >= 0) & (i + b + d + 1 <= n - 1)
+    assert interior.sum() > 60
+    assert np.max(np.abs(out[interior] - p(i[interior] + beta))) < 1e-12
+
+
+@pytest.mark.parametrize("m", [1, 2, 3])
+def test_resolved_mode_is_translated(orc, m):
+    # A resolved periodic mode is translated exactly up to the degree-17
+    # interpolation error, which is far below FP64 rounding here.
+    n = 256
+    i = np.arange(n)
+    th = 2 * math.pi * m / n
+    for beta in [0.4, -3.3, 40.6]:
+        out = orc.advect_line(np.cos(th * i + 0.2), 8, beta)
+        assert np.max(np.abs(out - np.cos(th * (i + beta) + 0.2))) < 1e-13
+
+
+@pytest.mark.parametrize("n,d", [(32, 8), (16, 4), (8, 1), (8, 0)])
+def test_dense_circulant_matches_stencil(orc, n, d):
+    # A = C(a_0 .. a_{n-1}): row i is the first row shifted right by i
+    # (Section 1.2), so A[i, k] = a[(k - i) mod n].
+    for beta in [0.37, -2.5, 9.99, -13.01]:
+        a = orc.circulant_row(n, d, beta)
+        A = np.array([[a[(k - i) % n] for k in range(n)] for i in range(n)])
+        u = RNG.standard_normal(n)
+        assert np.allclose(A @ u, orc.advect_line(u, d, beta), rtol=0, atol=1e-13)
+        assert np.count_nonzero(a) == 2 * d + 2 or beta == round(beta)
+
+
+# ------------------------------------------------------------------ field
+
+def test_poisson_closed_form(orc):
+    # dE/dx = rho - mean(rho); rho = 1 + a cos(k x) + c sin(3 k x)
+    # gives E = (a/k) sin(k x) - c/(3k) cos(3 k x).
+    w = workloads.landau_weak()
+    o = orc.Oracle(w)
+    x = o.x()
+    k = 0.5
+    rho = 1.0 + 0.3 * np.cos(k * x) + 0.05 * np.sin(3 * k * x)
+    E = o.poisson(rho)
+    ex = 0.3 / k * np.sin(k * x) - 0.05 / (3 * k) * np.cos(3 * k * x)
+    assert np.max(np.abs(E - ex)) < 1e-13
+    assert abs(E.mean()) < 1e-15
+
+
+def test_poisson_drops_mean_and_nyquist(orc):
+    w = workloads.landau_weak()
+    o = orc.Oracle(w)
+    rho = 3.0 + (-1.0) ** np.arange(w.nx)   # mean plus Nyquist only
+    assert np.max(np.abs(o.poisson(rho))) < 1e-13
+
+
+def test_rho_of_maxwellian_product(orc):
+    # int f_M dv = 1 up to the Gaussian tail beyond |v| = 6 (< 2e-9) and the
+    # spectrally small rectangle-rule error.
+    w = workloads.landau_weak()
+    o = orc.Oracle(w).init()
+    x = o.x()
+    assert np.max(np.abs(o.rho - (1.0 + 0.01 * np.cos(0.5 * x)))) < 5e-9
+
+
+# ------------------------------------------------------------------ 2D runs
+
+def test_free_streaming_exact(orc):
+    w = workloads.free_streaming(64, 64, 20)
+    o = orc.Oracle(w).init()
+    o.step(w.nsteps)
+    x, v = o.x()[:, None], o.v()[None, :]
+    t = w.nsteps * w.dt
+    fm = np.exp(-v ** 2 / 2) / math.sqrt(2 * math.pi)
+    exact = (1 + 0.05 * np.cos(0.5 * (x - v * t) + 0.3)) * fm
+    assert np.max(np.abs(o.full_f() - exact)) < 1e-13
+
+
+def test_free_streaming_exact_deltaf(orc):
+    w = workloads.free_streaming(64, 64, 20).replace(precision="fp64_deltaf")
+    o = orc.Oracle(w).init()
+    o.step(w.nsteps)
+    x, v = o.x()[:, None], o.v()[None, :]
+    t = w.nsteps * w.dt
+    fm = np.exp(-v ** 2 / 2) / math.sqrt(2 * math.pi)
+    assert np.max(np.abs(o.f - 0.05 * np.cos(0.5 * (x - v * t) + 0.3) * fm)) < 1e-14
+
+
+def test_mass_conserved_plain(orc):
+    w = workloads.landau_strong().replace(nx=64, nv=128, precision="fp64_plain")
+    o = orc.Oracle(w).init()
+    m0 = o.f.sum()
+    o.step(20)
+    assert abs(o.f.sum() - m0) / abs(m0) < 1e-13
+
+
+def test_vadvect_deltaf_source_of_zero_perturbation(orc):
+    # delta f = 0 and a field E: the update is f_eq(v - tau E) - f_eq(v)
+    # exactly (Section 3.1, the evaluation term).
+    w = workloads.landau_weak().replace(precision="fp64_deltaf")
+    o = orc.Oracle(w)
+    E = 0.3 * np.sin(o.x())
+    tau = 0.05
+    o.advect_v(tau, E)
+    v = o.v()[None, :]
+    fm = lambda vv: np.exp(-vv ** 2 / 2) / math.sqrt(2 * math.pi)
+    assert np.max(np.abs(o.f - (fm(v - tau * E[:, None]) - fm(v)))) < 1e-15
+
+
+def test_plain_and_deltaf_agree(orc):
+    # Same physics in both forms; they differ by the interpolation error of
+    # f_eq and its periodic seam, both tiny at |v| = 6.
+    w = workloads.landau_weak()
+    a = orc.Oracle(w, deltaf=False).init()
+    b = orc.Oracle(w, deltaf=True).init()
+    a.step(10)
+    b.step(10)
+    fa, fb = a.full_f(), b.full_f()
+    assert np.max(np.abs(fa - fb)) / np.max(np.abs(fa)) < 1e-8
+    assert np.max(np.abs(a.E - b.E)) / np.max(np.abs(a.E)) < 1e-6
+
+
+def test_strang_is_second_order(orc):
+    # Error at fixed t against a fine-dt run shrinks ~4x per halving of dt;
+    # a first-order (Lie) ordering of the substeps would give ~2x.
+    base = workloads.landau_strong().replace(nx=32, nv=64, vmin=-6.0, vmax=6.0,
+                                             precision="fp64_plain")
+    T = 1.6
+
+    def run(dt):
+        o = orc.Oracle(base.replace(dt=dt)).init()
+        o.step(int(round(T / dt)))
+        return o.f.copy()
+
+    ref = run(0.0125)
+    e = [np.max(np.abs(run(dt) - ref)) for dt in (0.2, 0.1, 0.05)]
+    r1, r2 = e[0] / e[1], e[1] / e[2]
+    assert 3.3 < r1 < 4.8 and 3.3 < r2 < 4.8, (e, r1, r2)
+
+
+def _paper():
+    with open(os.path.join(GOLDEN, "landau_paper.json")) as fh:
+        return json.load(fh)
+
+
+def test_landau_weak_rate(orc):
+    # Short run (t <= 10): rate within 5 % of the paper's value.
+    w = workloads.landau_weak()
+    o = orc.Oracle(w).init()
+    d = o.step(w.nsteps)
+    t = (np.arange(w.nsteps) + 1) * w.dt
+    gamma, omega, _ = orc.landau_fit(t, d[:, 0])
+    assert abs(-gamma - _paper()["gamma"]) / _paper()["gamma"] < 0.05
+    assert abs(omega - 1.4156) / 1.4156 < 0.01
+
+
+@pytest.mark.slow
+def test_landau_long_rate_and_counts(orc):
+    w = workloads.landau_long()
+    o = orc.Oracle(w).init()
+    d = o.step(w.nsteps)
+    t = (np.arange(w.nsteps) + 1) * w.dt
+    gamma, omega, peaks = orc.landau_fit(t, d[:, 0], 4.0, 36.0)
+    paper = _paper()
+    assert abs(-gamma - paper["gamma"]) / paper["gamma"] < 0.02
+    assert abs(omega - 1.4156) / 1.4156 < 0.005
+    # The paper's oscillation counts: n maxima reached by time t.
+    spacing = math.pi / omega
+    for rec in paper["oscillation_counts"]:
+        assert abs(rec["t"] / spacing - rec["count"]) < 1.0
+
+
+def test_landau_mass_and_field_history(orc):
+    w = workloads.landau_weak()
+    o = orc.Oracle(w).init()
+    d = o.step(30)
+    assert np.all(np.abs(d[:, 1] - d[0, 1]) < 1e-14)        # mass drift
+    assert np.all(d[:, 0] > 0) and d[-1, 0] < d[0, 0]        # damping
