@@ -1,0 +1,204 @@
+// Batched LDS-resident complex FFT for gfx950 (wave64), FP32 and FP64.
+//
+// One transform of length N (a power of two, 8 <= N <= 4096) is carried by
+// TPF = N / R threads that each hold R = min(N, 16) complex values in
+// registers.  The transform is a Stockham autosort sequence of passes of
+// radix 16 (the last pass takes the remaining factor 2, 4, 8 or 16); every
+// pass works on registers, and consecutive passes exchange data through LDS
+// (structure-of-arrays, one padding slot per 16 elements).
+//
+// Layouts (t = thread index within the transform, 0 <= t < TPF):
+//   input:  register r holds element t + r * TPF            (r < R)
+//   output: register i holds frequency t + TPF * kpos(i)    (i < R)
+// kpos is a compile-time permutation fixed by the last pass radix.
+//
+// Twiddle factors come from a per-length table tab[k] = exp(+i pi k / N),
+// k < 2N, built in FP64 on the host and rounded to the storage precision.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <type_traits>
+#include <utility>
+
+namespace vog {
+
+template <typename T>
+struct cx {
+    T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> cmul_conj(cx<T> a, cx<T> b) {  // a * conj(b)
+    return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> cscale(cx<T> a, T s) { return {a.re * s, a.im * s}; }
+
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
+constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
+
+// cos(2 pi j / 16), j = 0..15; sin(2 pi j / 16) = cos(2 pi (j - 4) / 16).
+constexpr double kCos16[16] = {
+    1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+    0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+    -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173,
+    0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613};
+
+// a * exp(DIR * 2 pi i K / R) for a compile-time K and R dividing 16.
+template <typename T, int DIR, int K, int R>
+__device__ __forceinline__ cx<T> twc(cx<T> a) {
+    constexpr int j = (((K % R) + R) % R) * (16 / R);
+    if constexpr (j == 0) {
+        return a;
+    } else if constexpr (j == 8) {
+        return {-a.re, -a.im};
+    } else if constexpr (j == 4) {  // exp(DIR i pi/2) = DIR i
+        if constexpr (DIR > 0) return {-a.im, a.re};
+        else return {a.im, -a.re};
+    } else if constexpr (j == 12) {  // exp(DIR i 3pi/2) = -DIR i
+        if constexpr (DIR > 0) return {a.im, -a.re};
+        else return {-a.im, a.re};
+    } else {
+        constexpr T c = (T)kCos16[j];
+        constexpr T s = (T)(DIR * kCos16[(j + 12) % 16]);
+        return {a.re * c - a.im * s, a.re * s + a.im * c};
+    }
+}
+
+// In-register DFT of length R (2, 4, 8 or 16), natural order in and out:
+// v[k] <- sum_n v[n] exp(DIR 2 pi i n k / R).
+template <typename T, int DIR, int R>
+__device__ __forceinline__ void dft(cx<T> *v) {
+    if constexpr (R == 1) {
+        return;
+    } else if constexpr (R == 2) {
+        cx<T> a = v[0], b = v[1];
+        v[0] = a + b;
+        v[1] = a - b;
+    } else if constexpr (R == 4) {
+        cx<T> a0 = v[0] + v[2], a1 = v[0] - v[2], a2 = v[1] + v[3];
+        cx<T> a3 = twc<T, DIR, 1, 4>(v[1] - v[3]);
+        v[0] = a0 + a2;
+        v[2] = a0 - a2;
+        v[1] = a1 + a3;
+        v[3] = a1 - a3;
+    } else {
+        constexpr int H = R / 2;
+        cx<T> e[H], o[H];
+        static_for<0, H>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            e[k] = v[2 * k];
+            o[k] = v[2 * k + 1];
+        });
+        dft<T, DIR, H>(e);
+        dft<T, DIR, H>(o);
+        static_for<0, H>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            cx<T> tt = twc<T, DIR, k, R>(o[k]);
+            v[k] = e[k] + tt;
+            v[k + H] = e[k] - tt;
+        });
+    }
+}
+
+template <typename T, int N>
+struct Fft {
+    static_assert(N >= 8 && N <= 4096 && (N & (N - 1)) == 0, "N must be a power of two in [8, 4096]");
+    static constexpr int R = N < 16 ? N : 16;
+    static constexpr int TPF = N / R;
+    static constexpr int LOG = ilog2(N);
+    static constexpr int NPASS = (LOG + 3) / 4;
+    static constexpr int LAST = N / ipow(16, NPASS - 1);
+    static constexpr int LDSN = N + N / 16;  // padded SoA length
+
+    static constexpr int radix(int p) { return p == NPASS - 1 ? LAST : 16; }
+    static constexpr int ns(int p) { return ipow(16, p); }
+    // frequency index (in units of TPF, offset t) held by register i after the last pass
+    static constexpr int kpos(int i) { return i / LAST + (i % LAST) * (R / LAST); }
+    static constexpr int kinv(int k) {  // register index holding position k
+        for (int i = 0; i < R; ++i)
+            if (kpos(i) == k) return i;
+        return -1;
+    }
+    static __device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
+
+    // One radix pass on registers (twiddles, then DFT of each group).
+    template <int DIR, int P>
+    static __device__ __forceinline__ void pass(cx<T> (&v)[R], int t, const cx<T> *__restrict__ tab) {
+        constexpr int RP = radix(P), NS = ns(P);
+        static_for<0, R / RP>([&](auto uc) {
+            constexpr int u = decltype(uc)::value;
+            if constexpr (NS > 1) {
+                const int jb = t + u * TPF;
+                const int k = jb & (NS - 1);
+                constexpr int SC = 2 * N / (NS * RP);  // table stride: exp(2 pi i r k / (NS RP))
+                static_for<1, RP>([&](auto rc) {
+                    constexpr int r = decltype(rc)::value;
+                    const cx<T> w = tab[(r * k * SC) & (2 * N - 1)];
+                    if constexpr (DIR > 0) v[u * RP + r] = cmul(v[u * RP + r], w);
+                    else v[u * RP + r] = cmul_conj(v[u * RP + r], w);
+                });
+            }
+            dft<T, DIR, RP>(&v[u * RP]);
+        });
+    }
+
+    // Stockham exchange after pass P: store in autosort order, reload in the
+    // layout of pass P + 1.  All threads of the block must call it.
+    template <int P>
+    static __device__ __forceinline__ void exchange(cx<T> (&v)[R], int t, T *lre, T *lim) {
+        constexpr int RP = radix(P), NS = ns(P), RQ = radix(P + 1);
+        __syncthreads();
+        static_for<0, R / RP>([&](auto uc) {
+            constexpr int u = decltype(uc)::value;
+            const int jb = t + u * TPF;
+            const int k = jb & (NS - 1);
+            const int base = (jb - k) * RP + k;
+            static_for<0, RP>([&](auto rc) {
+                constexpr int r = decltype(rc)::value;
+                const int idx = pad(base + r * NS);
+                lre[idx] = v[u * RP + r].re;
+                lim[idx] = v[u * RP + r].im;
+            });
+        });
+        __syncthreads();
+        static_for<0, R / RQ>([&](auto uc) {
+            constexpr int u = decltype(uc)::value;
+            static_for<0, RQ>([&](auto rc) {
+                constexpr int r = decltype(rc)::value;
+                const int idx = pad(t + u * TPF + r * (N / RQ));
+                v[u * RQ + r] = cx<T>{lre[idx], lim[idx]};
+            });
+        });
+    }
+
+    // Full transform: X_m = sum_n x_n exp(DIR 2 pi i n m / N), unnormalised.
+    template <int DIR>
+    static __device__ __forceinline__ void run(cx<T> (&v)[R], int t, T *lre, T *lim,
+                                               const cx<T> *__restrict__ tab) {
+        static_for<0, NPASS>([&](auto pc) {
+            constexpr int p = decltype(pc)::value;
+            pass<DIR, p>(v, t, tab);
+            if constexpr (p + 1 < NPASS) exchange<p>(v, t, lre, lim);
+        });
+    }
+};
+
+}  // namespace vog

@@ -1,0 +1,591 @@
+// HIP kernels of the split step (gfx950, wave64).
+//
+//  sweep_kernel     one constant advection (Section 1.2) for a batch of lines:
+//                   forward FFT of two real lines packed as one complex line,
+//                   multiply by the diagonal of the circulant in Fourier space,
+//                   inverse FFT, integer part of the shift applied as an exact
+//                   cyclic index offset on the store, delta-f source term
+//                   (Section 3.1) on v-sweeps.
+//  transpose_kernel tiled LDS transpose between the v-fastest and x-fastest
+//                   layouts; the x->v direction also emits FP64 partial sums
+//                   of f over 64 velocities for rho = int f dv.
+//  field_kernel     FP64 rho, FFT Poisson solve with mode 0 set to zero
+//                   (Section 3.2), E, and the per-step diagnostics record.
+//  rho_v_kernel, moments kernels, init and fill helpers.
+#include "fft.hpp"
+#include "vog_internal.hpp"
+
+#include <math.h>
+
+namespace vog {
+
+// ----------------------------------------------------------------- helpers
+
+// Lagrange 2d+1 coefficient of node q for the fractional shift s in [0, 1)
+// (Section 1.2): prod_{k != q} (s - k) / (q - k), nodes k = -d .. d+1.
+__device__ __forceinline__ double lagrange_weight(int d, int q, double s) {
+    if (q < -d || q > d + 1) return 0.0;
+    double num = 1.0, den = 1.0;
+    for (int k = -d; k <= d + 1; ++k) {
+        if (k == q) continue;
+        num *= s - (double)k;
+        den *= (double)(q - k);
+    }
+    return num / den;
+}
+
+// beta = b + s with b integer and s in [0, 1).
+__device__ __forceinline__ void split_shift(double beta, long long &b, double &s) {
+    double fb = floor(beta);
+    double r = beta - fb;
+    if (r >= 1.0) {
+        r = 0.0;
+        fb += 1.0;
+    }
+    b = (long long)fb;
+    s = r;
+}
+
+template <typename T>
+__device__ __forceinline__ T expm1_t(T x);
+template <>
+__device__ __forceinline__ float expm1_t<float>(float x) { return expm1f(x); }
+template <>
+__device__ __forceinline__ double expm1_t<double>(double x) { return expm1(x); }
+
+// ----------------------------------------------------------------- sweep
+
+// KIND 0: v-advection by tau = b.a[sim] with field E (lines are x-columns of
+// f, length nv).  KIND 1: x-advection by dt = b.a[sim] (lines are v-rows of
+// the transposed copy g, length nx).
+template <typename T, int N, int KIND>
+__global__ __launch_bounds__(256) void sweep_kernel(const Batch b) {
+    using F = Fft<T, N>;
+    constexpr int R = F::R, TPF = F::TPF, PPB = 256 / TPF;
+    __shared__ T lds[PPB][2][F::LDSN];
+    __shared__ T wsh[PPB][2][kTaps];
+
+    const SimDev &S = *b.s[blockIdx.y];
+    const int nlines = KIND == 0 ? S.nx : S.nv;
+    const int npairs = nlines >> 1;
+    if ((int)blockIdx.x * PPB >= npairs) return;  // whole block idle
+
+    const int slot = threadIdx.x / TPF;
+    const int t = threadIdx.x % TPF;
+    const int pair = blockIdx.x * PPB + slot;
+    const bool active = pair < npairs;
+    const int lineA = active ? 2 * pair : 0;
+    const int lineB = lineA + 1;
+    T *lre = lds[slot][0];
+    T *lim = lds[slot][1];
+    const cx<T> *tab = (const cx<T> *)(KIND == 0 ? S.tab_v : S.tab_x);
+    T *data = (T *)(KIND == 0 ? S.f : S.g);
+    T *pA = data + (size_t)lineA * N;
+    T *pB = data + (size_t)lineB * N;
+
+    // Shift of each line, FP64: v-sweep beta = -tau E_i / dv, x-sweep
+    // beta = -v_j dt / dx.
+    const double arg = b.a[blockIdx.y];
+    double EA = 0.0, EB = 0.0, betaA, betaB;
+    if constexpr (KIND == 0) {
+        EA = S.E[lineA];
+        EB = S.E[lineB];
+        betaA = -arg * EA * S.inv_dv;
+        betaB = -arg * EB * S.inv_dv;
+    } else {
+        betaA = -(S.vmin + lineA * S.dv) * arg * S.inv_dx;
+        betaB = -(S.vmin + lineB * S.dv) * arg * S.inv_dx;
+    }
+    long long bA, bB;
+    double sA, sB;
+    split_shift(betaA, bA, sA);
+    split_shift(betaB, bB, sB);
+
+    // Weights of the pair, combined for the packed transform:
+    // wP = (wA + wB) / (2N), wQ = (wA - wB) / (2N) (1/N folds the inverse FFT scale).
+    for (int qi = t; qi < kTaps; qi += TPF) {
+        const int q = qi - kDMax;
+        const double wa = lagrange_weight(S.d, q, sA);
+        const double wb = lagrange_weight(S.d, q, sB);
+        const double sc = 0.5 / (double)N;
+        wsh[slot][0][qi] = (T)((wa + wb) * sc);
+        wsh[slot][1][qi] = (T)((wa - wb) * sc);
+    }
+
+    // Load the two lines packed as z = uA + i uB.
+    cx<T> v[R];
+    static_for<0, R>([&](auto rc) {
+        constexpr int r = decltype(rc)::value;
+        const int j = t + r * TPF;
+        v[r] = active ? cx<T>{pA[j], pB[j]} : cx<T>{(T)0, (T)0};
+    });
+
+    F::template run<-1>(v, t, lre, lim, tab);  // v[i] = Z[t + TPF kpos(i)]
+
+    // Partner values conj(Z[N - m]) needed to separate the two real lines.
+    cx<T> W[R];
+    if constexpr (TPF > 1) {
+        __syncthreads();
+        static_for<0, R>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            const int idx = F::pad(t + TPF * F::kpos(i));
+            lre[idx] = v[i].re;
+            lim[idx] = v[i].im;
+        });
+        __syncthreads();
+        static_for<0, R>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            const int m = t + TPF * F::kpos(i);
+            const int idx = F::pad((N - m) & (N - 1));
+            W[i] = cx<T>{lre[idx], -lim[idx]};
+        });
+    } else {
+        __syncthreads();  // weights visible
+        static_for<0, R>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            constexpr int mm = (N - F::kpos(i)) & (N - 1);
+            constexpr int ip = F::kinv(mm);
+            W[i] = cx<T>{v[ip].re, -v[ip].im};
+        });
+    }
+
+    // Symbol of the fractional-shift kernel for the modes m = t + k TPF:
+    //   S_m = sum_q w_q exp(2 pi i m q / N) = DFT_R^+ (H)[k],
+    //   H_c = sum_{q = c mod R} w_q exp(2 pi i t q / N).
+    // The packed product is Y_m = P_m Z_m + Q_m conj(Z_{N-m}) with P, Q the
+    // symbols of wP, wQ.
+    cx<T> Y[R];
+    {
+        cx<T> H[R];
+        static_for<0, R>([&](auto cc) { H[decltype(cc)::value] = cx<T>{(T)0, (T)0}; });
+        static_for<0, kTaps>([&](auto qc) {
+            constexpr int qi = decltype(qc)::value;
+            constexpr int q = qi - kDMax;
+            constexpr int c = ((q % R) + R) % R;
+            const T w = wsh[slot][0][qi];
+            if constexpr (q == 0) {
+                H[c].re += w;
+            } else {
+                const int aq = q < 0 ? -q : q;
+                cx<T> e = tab[(2 * t * aq) & (2 * N - 1)];
+                if constexpr (q < 0) e.im = -e.im;
+                H[c].re += w * e.re;
+                H[c].im += w * e.im;
+            }
+        });
+        dft<T, 1, R>(H);
+        static_for<0, R>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            constexpr int k = F::kpos(i);
+            Y[k] = cmul(H[k], v[i]);
+        });
+    }
+    {
+        cx<T> H[R];
+        static_for<0, R>([&](auto cc) { H[decltype(cc)::value] = cx<T>{(T)0, (T)0}; });
+        static_for<0, kTaps>([&](auto qc) {
+            constexpr int qi = decltype(qc)::value;
+            constexpr int q = qi - kDMax;
+            constexpr int c = ((q % R) + R) % R;
+            const T w = wsh[slot][1][qi];
+            if constexpr (q == 0) {
+                H[c].re += w;
+            } else {
+                const int aq = q < 0 ? -q : q;
+                cx<T> e = tab[(2 * t * aq) & (2 * N - 1)];
+                if constexpr (q < 0) e.im = -e.im;
+                H[c].re += w * e.re;
+                H[c].im += w * e.im;
+            }
+        });
+        dft<T, 1, R>(H);
+        static_for<0, R>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            constexpr int k = F::kpos(i);
+            Y[k] = Y[k] + cmul(H[k], W[i]);
+        });
+    }
+
+    F::template run<1>(Y, t, lre, lim, tab);  // Y[i] = y[t + TPF kpos(i)]
+
+    if (!active) return;
+
+    // Store: unshifted index j goes to line position (j - b) mod N.
+    const int bmA = (int)(bA & (N - 1));
+    const int bmB = (int)(bB & (N - 1));
+    if constexpr (KIND == 0) {
+        if (S.deltaf) {
+            // f_eq(v - tau E) - f_eq(v) = sum_g f_g(v) expm1(A_g (v - c_g) + B_g),
+            // A_g = tau E / sigma_g^2, B_g = -(tau E)^2 / (2 sigma_g^2).
+            T Ag[VOG_MAX_FEQ][2], Bg[VOG_MAX_FEQ][2], cg[VOG_MAX_FEQ];
+            const double dA = arg * EA, dB = arg * EB;
+            for (int g = 0; g < VOG_MAX_FEQ; ++g) {
+                const double is2 = g < S.n_feq ? S.feq_inv_s2[g] : 0.0;
+                Ag[g][0] = (T)(dA * is2);
+                Ag[g][1] = (T)(dB * is2);
+                Bg[g][0] = (T)(-0.5 * dA * dA * is2);
+                Bg[g][1] = (T)(-0.5 * dB * dB * is2);
+                cg[g] = (T)S.feq_c[g];
+            }
+            const T *fg = (const T *)S.feq_g;
+            const T vmin = (T)S.vmin, dv = (T)S.dv;
+            const int nfeq = S.n_feq;
+            static_for<0, R>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                const int j = t + TPF * F::kpos(i);
+                const int posA = (j - bmA) & (N - 1);
+                const int posB = (j - bmB) & (N - 1);
+                const T vA = vmin + (T)posA * dv;
+                const T vB = vmin + (T)posB * dv;
+                T srcA = (T)0, srcB = (T)0;
+                for (int g = 0; g < nfeq; ++g) {
+                    srcA += fg[g * N + posA] * expm1_t<T>(Ag[g][0] * (vA - cg[g]) + Bg[g][0]);
+                    srcB += fg[g * N + posB] * expm1_t<T>(Ag[g][1] * (vB - cg[g]) + Bg[g][1]);
+                }
+                pA[posA] = Y[i].re + srcA;
+                pB[posB] = Y[i].im + srcB;
+            });
+            return;
+        }
+    }
+    static_for<0, R>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        const int j = t + TPF * F::kpos(i);
+        pA[(j - bmA) & (N - 1)] = Y[i].re;
+        pB[(j - bmB) & (N - 1)] = Y[i].im;
+    });
+}
+
+template <typename T, int N, int KIND>
+static void launch_sweep(const Batch &b, int max_lines, hipStream_t st) {
+    constexpr int PPB = 256 / Fft<T, N>::TPF;
+    const int blocks = (max_lines / 2 + PPB - 1) / PPB;
+    hipLaunchKernelGGL((sweep_kernel<T, N, KIND>), dim3(blocks, b.n), dim3(256), 0, st, b);
+}
+
+template <typename T, int KIND, int... L>
+static LaunchFn pick_sweep(int logn, std::integer_sequence<int, L...>) {
+    LaunchFn fns[] = {&launch_sweep<T, (8 << L), KIND>...};
+    return fns[logn - 3];
+}
+
+LaunchFn sweep_launcher(bool fp64, int n, bool vsweep) {
+    const int logn = ilog2(n);
+    if (n < VOG_MIN_N || n > VOG_MAX_N || (1 << logn) != n) return nullptr;
+    using Seq = std::make_integer_sequence<int, 10>;
+    if (fp64) return vsweep ? pick_sweep<double, 0>(logn, Seq{}) : pick_sweep<double, 1>(logn, Seq{});
+    return vsweep ? pick_sweep<float, 0>(logn, Seq{}) : pick_sweep<float, 1>(logn, Seq{});
+}
+
+// ----------------------------------------------------------------- transpose
+
+// TO_V false: f [nx][nv] -> g [nv][nx].  TO_V true: g [nv][nx] -> f [nx][nv]
+// and part[jt][i] = sum of the tile's (up to 64) velocities of column i,
+// accumulated in FP64 in a fixed order.
+template <typename T, bool TO_V>
+__global__ __launch_bounds__(256) void transpose_kernel(const Batch b) {
+    __shared__ T tile[kTile][kTile + 1];
+    const SimDev &S = *b.s[blockIdx.y];
+    const int rows = TO_V ? S.nv : S.nx;
+    const int cols = TO_V ? S.nx : S.nv;
+    const T *in = (const T *)(TO_V ? S.g : S.f);
+    T *out = (T *)(TO_V ? S.f : S.g);
+    const int tilesC = (cols + kTile - 1) / kTile;
+    const int tilesR = (rows + kTile - 1) / kTile;
+    const int tr = blockIdx.x / tilesC, tc = blockIdx.x % tilesC;
+    if (tr >= tilesR) return;
+    const int r0 = tr * kTile, c0 = tc * kTile;
+    const int tx = threadIdx.x & (kTile - 1), ty = threadIdx.x / kTile;
+    for (int rr = ty; rr < kTile; rr += 256 / kTile) {
+        const int r = r0 + rr, c = c0 + tx;
+        if (r < rows && c < cols) tile[rr][tx] = in[(size_t)r * cols + c];
+    }
+    __syncthreads();
+    for (int cc = ty; cc < kTile; cc += 256 / kTile) {
+        const int c = c0 + cc, r = r0 + tx;
+        if (r < rows && c < cols) out[(size_t)c * rows + r] = tile[tx][cc];
+    }
+    if constexpr (TO_V) {
+        if (threadIdx.x < kTile) {
+            const int c = c0 + threadIdx.x;
+            if (c < cols) {
+                const int nr = rows - r0 < kTile ? rows - r0 : kTile;
+                double acc = 0.0;
+                for (int rr = 0; rr < nr; ++rr) acc += (double)tile[rr][threadIdx.x];
+                S.part[(size_t)tr * cols + c] = acc;
+            }
+        }
+    }
+}
+
+void launch_transpose(bool fp64, bool to_v, const Batch &b, int max_tiles, hipStream_t st) {
+    dim3 grid(max_tiles, b.n), block(256);
+    if (fp64) {
+        if (to_v) hipLaunchKernelGGL((transpose_kernel<double, true>), grid, block, 0, st, b);
+        else hipLaunchKernelGGL((transpose_kernel<double, false>), grid, block, 0, st, b);
+    } else {
+        if (to_v) hipLaunchKernelGGL((transpose_kernel<float, true>), grid, block, 0, st, b);
+        else hipLaunchKernelGGL((transpose_kernel<float, false>), grid, block, 0, st, b);
+    }
+}
+
+// ----------------------------------------------------------------- field solve
+
+// One block per sim, TPF = N/16 threads (N = nx).  rho_i = dv sum_p part[p][i]
+// + feq_const; rho_hat = FFT(rho); E_hat_m = rho_hat_m / (i k_m), with
+// E_hat_0 = E_hat_{N/2} = 0 (Section 3.2, Fourier variant); E = iFFT / N.
+// Writes the step's diagnostics record.
+template <int N>
+constexpr int kFieldThreads = Fft<double, N>::TPF;
+
+template <int N>
+__global__ __launch_bounds__(kFieldThreads<N>) void field_kernel(const Batch b) {
+    using F = Fft<double, N>;
+    constexpr int R = F::R, TPF = F::TPF;
+    __shared__ double lre[F::LDSN], lim[F::LDSN];
+    __shared__ double red[TPF];
+    __shared__ double rho01[3];
+    __shared__ int bad[1];
+
+    const SimDev &S = *b.s[blockIdx.x];
+    const int t = threadIdx.x;
+    const cx<double> *tab = (const cx<double> *)S.tab_x64;
+    const int nparts = b.nparts[blockIdx.x];
+    if (t == 0) bad[0] = 0;
+
+    cx<double> v[R];
+    static_for<0, R>([&](auto rc) {
+        constexpr int r = decltype(rc)::value;
+        const int i = t + r * TPF;
+        double acc = 0.0;
+        for (int p = 0; p < nparts; ++p) acc += S.part[(size_t)p * N + i];
+        v[r] = cx<double>{acc * S.dv + S.feq_const, 0.0};
+    });
+    F::template run<-1>(v, t, lre, lim, tab);
+
+    // rho_hat_0 and rho_hat_1 (unnormalised here).
+    static_for<0, R>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        const int m = t + TPF * F::kpos(i);
+        if (m == 0) rho01[0] = v[i].re;
+        if (m == 1) {
+            rho01[1] = v[i].re;
+            rho01[2] = v[i].im;
+        }
+    });
+
+    cx<double> Y[R];
+    const double twopi_L = 2.0 * M_PI / S.L;
+    static_for<0, R>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        constexpr int k = F::kpos(i);
+        const int m = t + TPF * k;
+        const int mt = 2 * m < N ? m : m - N;
+        if (m == 0 || 2 * m == N || S.field_zero) {
+            Y[k] = cx<double>{0.0, 0.0};
+        } else {
+            const double km = twopi_L * (double)mt;
+            Y[k] = cx<double>{v[i].im / km, -v[i].re / km};
+        }
+    });
+    F::template run<1>(Y, t, lre, lim, tab);
+
+    double e2 = 0.0;
+    const double invn = 1.0 / (double)N;
+    static_for<0, R>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        const int j = t + TPF * F::kpos(i);
+        const double e = Y[i].re * invn;
+        S.E[j] = e;
+        e2 += e * e;
+        if (!isfinite(e)) bad[0] = 1;
+    });
+    red[t] = e2;
+    __syncthreads();
+    for (int h = TPF / 2; h > 0; h >>= 1) {
+        if (t < h) red[t] += red[t + h];
+        __syncthreads();
+    }
+    if (t == 0) {
+        vog_diag d;
+        d.step = b.step[blockIdx.x];
+        d.t = b.t[blockIdx.x];
+        d.normE = sqrt(S.dx * red[0]);
+        d.rho0 = rho01[0] * invn;
+        d.abs_rho1 = sqrt(rho01[1] * rho01[1] + rho01[2] * rho01[2]) * invn;
+        d.l2 = __builtin_nan("");
+        d.energy = __builtin_nan("");
+        d.finite = bad[0] ? 0 : 1;
+        d.reserved = 0;
+        S.ring[d.step % kRingCap] = d;
+    }
+}
+
+template <int N>
+static void launch_field(const Batch &b, int, hipStream_t st) {
+    hipLaunchKernelGGL((field_kernel<N>), dim3(b.n), dim3(Fft<double, N>::TPF), 0, st, b);
+}
+
+template <int... L>
+static LaunchFn pick_field(int logn, std::integer_sequence<int, L...>) {
+    LaunchFn fns[] = {&launch_field<(8 << L)>...};
+    return fns[logn - 3];
+}
+
+LaunchFn field_launcher(int nx) {
+    const int logn = ilog2(nx);
+    if (nx < VOG_MIN_N || nx > VOG_MAX_N || (1 << logn) != nx) return nullptr;
+    return pick_field(logn, std::make_integer_sequence<int, 10>{});
+}
+
+// ----------------------------------------------------------------- rho (v layout)
+
+// part[i] = sum_j f[i][j] in FP64 with a fixed reduction order (one block per
+// x-column); used when the field is computed from a freshly set f.
+template <typename T>
+__global__ __launch_bounds__(256) void rho_v_kernel(const Batch b) {
+    __shared__ double red[256];
+    const SimDev &S = *b.s[blockIdx.y];
+    const int i = blockIdx.x;
+    if (i >= S.nx) return;
+    const T *row = (const T *)S.f + (size_t)i * S.nv;
+    double acc = 0.0;
+    for (int j = threadIdx.x; j < S.nv; j += 256) acc += (double)row[j];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) S.part[i] = red[0];
+}
+
+void launch_rho_v(bool fp64, const Batch &b, int max_nx, hipStream_t st) {
+    if (fp64) hipLaunchKernelGGL((rho_v_kernel<double>), dim3(max_nx, b.n), dim3(256), 0, st, b);
+    else hipLaunchKernelGGL((rho_v_kernel<float>), dim3(max_nx, b.n), dim3(256), 0, st, b);
+}
+
+// ----------------------------------------------------------------- moments
+
+// mom[i] = (sum_j f_ij^2, sum_j f_ij v_j^2) of the full f (f_eq added back
+// for delta f), FP64, fixed order.
+template <typename T>
+__global__ __launch_bounds__(256) void moments_line_kernel(const Batch b) {
+    __shared__ double r1[256], r2[256];
+    const SimDev &S = *b.s[blockIdx.y];
+    const int i = blockIdx.x;
+    if (i >= S.nx) return;
+    const T *row = (const T *)S.f + (size_t)i * S.nv;
+    double a1 = 0.0, a2 = 0.0;
+    for (int j = threadIdx.x; j < S.nv; j += 256) {
+        double f = (double)row[j];
+        if (S.deltaf) f += S.feq64[j];
+        const double vj = S.vmin + j * S.dv;
+        a1 += f * f;
+        a2 += f * vj * vj;
+    }
+    r1[threadIdx.x] = a1;
+    r2[threadIdx.x] = a2;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            r1[threadIdx.x] += r1[threadIdx.x + h];
+            r2[threadIdx.x] += r2[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        S.mom[2 * i] = r1[0];
+        S.mom[2 * i + 1] = r2[0];
+    }
+}
+
+// L2 = dx dv sum f^2; energy = dx dv sum f v^2 / 2 + dx / 2 sum E^2
+// (Section 4.2), written into the step's diagnostics record.
+__global__ __launch_bounds__(256) void moments_final_kernel(const Batch b) {
+    __shared__ double r1[256], r2[256], r3[256];
+    const SimDev &S = *b.s[blockIdx.x];
+    double a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    for (int i = threadIdx.x; i < S.nx; i += 256) {
+        a1 += S.mom[2 * i];
+        a2 += S.mom[2 * i + 1];
+        a3 += S.E[i] * S.E[i];
+    }
+    r1[threadIdx.x] = a1;
+    r2[threadIdx.x] = a2;
+    r3[threadIdx.x] = a3;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            r1[threadIdx.x] += r1[threadIdx.x + h];
+            r2[threadIdx.x] += r2[threadIdx.x + h];
+            r3[threadIdx.x] += r3[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        vog_diag &d = S.ring[b.step[blockIdx.x] % kRingCap];
+        d.l2 = S.dx * S.dv * r1[0];
+        d.energy = 0.5 * S.dx * S.dv * r2[0] + 0.5 * S.dx * r3[0];
+    }
+}
+
+void launch_moments(bool fp64, const Batch &b, int max_nx, hipStream_t st) {
+    if (fp64) hipLaunchKernelGGL((moments_line_kernel<double>), dim3(max_nx, b.n), dim3(256), 0, st, b);
+    else hipLaunchKernelGGL((moments_line_kernel<float>), dim3(max_nx, b.n), dim3(256), 0, st, b);
+    hipLaunchKernelGGL(moments_final_kernel, dim3(b.n), dim3(256), 0, st, b);
+}
+
+// ----------------------------------------------------------------- init / fill
+
+struct InitArgs {
+    int nmodes;
+    double amp[8], kx[8], ph[8];
+};
+
+// f0 = (1 + sum_m amp_m cos(kx_m x_i + ph_m)) f_eq(v_j); delta f stores the
+// perturbation part only.
+template <typename T>
+__global__ __launch_bounds__(256) void init_kernel(const SimDev *sp, const InitArgs a) {
+    const SimDev &S = *sp;
+    const size_t cells = (size_t)S.nx * S.nv;
+    for (size_t idx = blockIdx.x * (size_t)256 + threadIdx.x; idx < cells;
+         idx += (size_t)gridDim.x * 256) {
+        const int i = (int)(idx / S.nv), j = (int)(idx % S.nv);
+        const double x = i * S.dx;
+        double p = 0.0;
+        for (int m = 0; m < a.nmodes; ++m) p += a.amp[m] * cos(a.kx[m] * x + a.ph[m]);
+        const double fe = S.feq64[j];
+        ((T *)S.f)[idx] = (T)(S.deltaf ? p * fe : (1.0 + p) * fe);
+    }
+}
+
+void launch_init(bool fp64, const SimDev *s, int cells, int nmodes, const double *amp,
+                 const double *kx, const double *ph, hipStream_t st) {
+    InitArgs a{};
+    a.nmodes = nmodes;
+    for (int m = 0; m < nmodes; ++m) {
+        a.amp[m] = amp[m];
+        a.kx[m] = kx[m];
+        a.ph[m] = ph[m];
+    }
+    int blocks = (cells + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (fp64) hipLaunchKernelGGL((init_kernel<double>), dim3(blocks), dim3(256), 0, st, s, a);
+    else hipLaunchKernelGGL((init_kernel<float>), dim3(blocks), dim3(256), 0, st, s, a);
+}
+
+__global__ __launch_bounds__(256) void fill_kernel(uint32_t *p, size_t nwords) {
+    for (size_t k = blockIdx.x * (size_t)256 + threadIdx.x; k < nwords; k += (size_t)gridDim.x * 256)
+        p[k] = 0u;
+}
+
+void launch_fill(void *p, size_t bytes, hipStream_t st) {
+    const size_t nwords = bytes / 4;
+    if (nwords == 0) return;
+    size_t blocks = (nwords + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks), dim3(256), 0, st, (uint32_t *)p, nwords);
+}
+
+}  // namespace vog

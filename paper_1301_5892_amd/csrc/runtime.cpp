@@ -1,0 +1,857 @@
+// Host runtime of libvog: configuration checks, workspace layout, FP64
+// tables, the stream-ordered step driver with grouped launches, readout,
+// checkpointing and kernel timing.  Implements include/vog.h.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "vog_internal.hpp"
+
+using namespace vog;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg) {
+    g_last_error = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                         \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(VOG_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));      \
+    } while (0)
+
+bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// exp(i pi k / n) for k < 2n, FP64, with the angle reduced to the first
+// octant so that symmetric entries are exact mirrors of each other.
+void unit_roots(int n, std::vector<double> &re, std::vector<double> &im) {
+    const int m = 2 * n;  // period
+    re.resize(m);
+    im.resize(m);
+    for (int k = 0; k < m; ++k) {
+        // angle = 2 pi k / m; use k mod m in eighths of a turn
+        long long num = (long long)k * 8;  // angle in units of (2 pi / 8) is num / m
+        int oct = (int)(num / m);
+        long long rem = num % m;  // within octant, fraction rem / m of pi/4
+        // reflect to first octant
+        double a;
+        int o = oct;
+        if (o % 2 == 0) a = (M_PI / 4.0) * ((double)rem / m);
+        else a = (M_PI / 4.0) * ((double)(m - rem) / m);
+        double c = cos(a), s = sin(a);
+        double x, y;
+        switch (o) {
+            case 0: x = c; y = s; break;
+            case 1: x = s; y = c; break;
+            case 2: x = -s; y = c; break;
+            case 3: x = -c; y = s; break;
+            case 4: x = -c; y = -s; break;
+            case 5: x = -s; y = -c; break;
+            case 6: x = s; y = -c; break;
+            default: x = c; y = -s; break;
+        }
+        re[k] = x;
+        im[k] = y;
+    }
+}
+
+struct Layout {
+    size_t f, g, E, part, mom, tab_x, tab_v, tab_x64, feq_g, feq64, ring, dev, total;
+};
+
+Layout layout_of(const vog_config &c) {
+    const size_t es = c.precision == VOG_FP32_DELTAF ? 4 : 8;
+    const size_t cells = (size_t)c.nx * c.nv;
+    const int nparts = (c.nv + kTile - 1) / kTile;
+    Layout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align256(off + bytes);
+        return at;
+    };
+    L.f = take(cells * es);
+    L.g = take(cells * es);
+    L.E = take(sizeof(double) * c.nx);
+    L.part = take(sizeof(double) * c.nx * (size_t)nparts);
+    L.mom = take(sizeof(double) * 2 * c.nx);
+    L.tab_x = take(2 * es * 2 * c.nx);
+    L.tab_v = take(2 * es * 2 * c.nv);
+    L.tab_x64 = take(2 * sizeof(double) * 2 * c.nx);
+    L.feq_g = take(es * VOG_MAX_FEQ * c.nv);
+    L.feq64 = take(sizeof(double) * c.nv);
+    L.ring = take(sizeof(vog_diag) * kRingCap);
+    L.dev = take(sizeof(SimDev));
+    L.total = off;
+    return L;
+}
+
+struct EventPair {
+    hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct vog_sim {
+    vog_config cfg;
+    Layout lay;
+    hipStream_t stream;
+    int device;
+    bool owns;
+    char *ws;
+    SimDev host_dev;       // host copy of the device constants
+    const SimDev *dev;     // device address
+    std::vector<double> feq64;  // f_eq(v_j), FP64
+    int64_t step;
+    double t;
+    int64_t diag_read;     // records consumed by vog_get_diag
+    bool fp64;
+    // profiling
+    bool prof;
+    std::vector<EventPair> ev[VOG_NUM_KINDS];
+    size_t ev_used[VOG_NUM_KINDS];
+    double ms[VOG_NUM_KINDS];
+    int64_t launches[VOG_NUM_KINDS];
+};
+
+namespace {
+
+int validate(const vog_config *c) {
+    if (!c) return fail(VOG_EINVAL, "config is NULL");
+    if (!is_pow2(c->nx) || c->nx < VOG_MIN_N || c->nx > VOG_MAX_N)
+        return fail(VOG_EINVAL, "nx must be a power of two in [8, 4096]");
+    if (!is_pow2(c->nv) || c->nv < VOG_MIN_N || c->nv > VOG_MAX_N)
+        return fail(VOG_EINVAL, "nv must be a power of two in [8, 4096]");
+    if (!(c->L > 0.0) || !isfinite(c->L)) return fail(VOG_EINVAL, "L must be finite and > 0");
+    if (!(c->vmin < c->vmax) || !isfinite(c->vmin) || !isfinite(c->vmax))
+        return fail(VOG_EINVAL, "need finite vmin < vmax");
+    if (c->degree < 1 || c->degree > VOG_MAX_DEGREE || c->degree % 2 == 0)
+        return fail(VOG_EINVAL, "degree must be odd in [1, 17]");
+    if (c->degree > c->nx - 1 || c->degree > c->nv - 1)
+        return fail(VOG_EINVAL, "degree must be <= min(nx, nv) - 1");
+    if (c->precision != VOG_FP64_PLAIN && c->precision != VOG_FP32_DELTAF &&
+        c->precision != VOG_FP64_DELTAF)
+        return fail(VOG_EINVAL, "unknown precision");
+    if (c->poisson != VOG_POISSON_FOURIER) return fail(VOG_EINVAL, "unknown Poisson solver");
+    if (c->field != VOG_FIELD_SELF_CONSISTENT && c->field != VOG_FIELD_ZERO)
+        return fail(VOG_EINVAL, "unknown field mode");
+    if (c->n_feq < 1 || c->n_feq > VOG_MAX_FEQ) return fail(VOG_EINVAL, "n_feq must be in [1, 4]");
+    for (int g = 0; g < c->n_feq; ++g) {
+        if (!isfinite(c->feq_a[g]) || !isfinite(c->feq_c[g]) || !(c->feq_sigma[g] > 0.0) ||
+            !isfinite(c->feq_sigma[g]))
+            return fail(VOG_EINVAL, "f_eq components need finite a, c and sigma > 0");
+    }
+    if (c->moments_every < 0) return fail(VOG_EINVAL, "moments_every must be >= 0");
+    return VOG_OK;
+}
+
+double feq_at(const vog_config &c, double v) {
+    double acc = 0.0;
+    for (int g = 0; g < c.n_feq; ++g) {
+        const double z = (v - c.feq_c[g]) / c.feq_sigma[g];
+        acc += c.feq_a[g] * exp(-0.5 * z * z);
+    }
+    return acc;
+}
+
+template <typename T>
+std::vector<T> interleave_roots(int n) {
+    std::vector<double> re, im;
+    unit_roots(n, re, im);
+    std::vector<T> out(4 * (size_t)n);
+    for (int k = 0; k < 2 * n; ++k) {
+        out[2 * k] = (T)re[k];
+        out[2 * k + 1] = (T)im[k];
+    }
+    return out;
+}
+
+int upload(void *dst, const void *src, size_t bytes, hipStream_t st) {
+    HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
+    return VOG_OK;
+}
+
+// Profiling helpers: events around one grouped launch of a kind.
+void prof_begin(vog_sim *s, int kind, EventPair **pp) {
+    *pp = nullptr;
+    if (!s->prof) return;
+    auto &v = s->ev[kind];
+    if (s->ev_used[kind] == v.size()) {
+        EventPair e;
+        if (hipEventCreate(&e.a) != hipSuccess) return;
+        if (hipEventCreate(&e.b) != hipSuccess) {
+            (void)hipEventDestroy(e.a);
+            return;
+        }
+        v.push_back(e);
+    }
+    EventPair *p = &v[s->ev_used[kind]++];
+    (void)hipEventRecord(p->a, s->stream);
+    *pp = p;
+}
+
+void prof_end(vog_sim *s, EventPair *p) {
+    if (p) (void)hipEventRecord(p->b, s->stream);
+}
+
+int collect_profile(vog_sim *s) {
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    for (int k = 0; k < VOG_NUM_KINDS; ++k) {
+        for (size_t i = 0; i < s->ev_used[k]; ++i) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, s->ev[k][i].a, s->ev[k][i].b));
+            s->ms[k] += ms;
+            s->launches[k] += 1;
+        }
+        s->ev_used[k] = 0;
+    }
+    return VOG_OK;
+}
+
+// Launch helpers over groups of sims that share a kernel instantiation.
+struct Group {
+    std::vector<vog_sim *> sims;
+    std::vector<double> arg;
+};
+
+template <typename Fn>
+int for_chunks(const Group &g, Fn &&fn) {
+    for (size_t base = 0; base < g.sims.size(); base += kMaxBatch) {
+        Batch b{};
+        b.n = (int)std::min<size_t>(kMaxBatch, g.sims.size() - base);
+        for (int k = 0; k < b.n; ++k) {
+            b.s[k] = g.sims[base + k]->dev;
+            b.a[k] = g.arg.empty() ? 0.0 : g.arg[base + k];
+        }
+        int rc = fn(b, base);
+        if (rc != VOG_OK) return rc;
+    }
+    return VOG_OK;
+}
+
+int check_launch() {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(VOG_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+    return VOG_OK;
+}
+
+// v-sweeps of all sims (tau per sim).
+int run_sweep(vog_sim *lead, const std::vector<vog_sim *> &sims, const std::vector<double> &arg,
+              bool vsweep) {
+    std::map<std::pair<int, int>, Group> groups;  // (fp64, line length)
+    for (size_t k = 0; k < sims.size(); ++k) {
+        vog_sim *s = sims[k];
+        auto key = std::make_pair((int)s->fp64, vsweep ? s->cfg.nv : s->cfg.nx);
+        groups[key].sims.push_back(s);
+        groups[key].arg.push_back(arg[k]);
+    }
+    for (auto &kv : groups) {
+        LaunchFn fn = sweep_launcher(kv.first.first != 0, kv.first.second, vsweep);
+        if (!fn) return fail(VOG_EINVAL, "no sweep kernel for this line length");
+        int rc = for_chunks(kv.second, [&](const Batch &b, size_t base) {
+            int maxl = 0;
+            for (int k = 0; k < b.n; ++k) {
+                const vog_sim *s = kv.second.sims[base + k];
+                maxl = std::max(maxl, vsweep ? s->cfg.nx : s->cfg.nv);
+            }
+            EventPair *p;
+            prof_begin(lead, vsweep ? K_SWEEP_V : K_SWEEP_X, &p);
+            fn(b, maxl, lead->stream);
+            prof_end(lead, p);
+            return check_launch();
+        });
+        if (rc != VOG_OK) return rc;
+    }
+    return VOG_OK;
+}
+
+int run_transpose(vog_sim *lead, const std::vector<vog_sim *> &sims, bool to_v) {
+    std::map<int, Group> groups;
+    for (vog_sim *s : sims) groups[(int)s->fp64].sims.push_back(s);
+    for (auto &kv : groups) {
+        int rc = for_chunks(kv.second, [&](const Batch &b, size_t base) {
+            int maxt = 0;
+            for (int k = 0; k < b.n; ++k) {
+                const vog_sim *s = kv.second.sims[base + k];
+                const int tiles = ((s->cfg.nx + kTile - 1) / kTile) * ((s->cfg.nv + kTile - 1) / kTile);
+                maxt = std::max(maxt, tiles);
+            }
+            EventPair *p;
+            prof_begin(lead, to_v ? K_T_XV : K_T_VX, &p);
+            launch_transpose(kv.first != 0, to_v, b, maxt, lead->stream);
+            prof_end(lead, p);
+            return check_launch();
+        });
+        if (rc != VOG_OK) return rc;
+    }
+    return VOG_OK;
+}
+
+// Field solve for all sims; nparts = number of partial rows in part.
+int run_field(vog_sim *lead, const std::vector<vog_sim *> &sims, const std::vector<int64_t> &stepno,
+              const std::vector<double> &tnow, bool from_transpose) {
+    std::map<int, std::vector<size_t>> groups;  // nx -> indices
+    for (size_t k = 0; k < sims.size(); ++k) groups[sims[k]->cfg.nx].push_back(k);
+    for (auto &kv : groups) {
+        LaunchFn fn = field_launcher(kv.first);
+        if (!fn) return fail(VOG_EINVAL, "no field kernel for this nx");
+        const auto &idx = kv.second;
+        for (size_t base = 0; base < idx.size(); base += kMaxBatch) {
+            Batch b{};
+            b.n = (int)std::min<size_t>(kMaxBatch, idx.size() - base);
+            for (int k = 0; k < b.n; ++k) {
+                const size_t i = idx[base + k];
+                b.s[k] = sims[i]->dev;
+                b.step[k] = stepno[i];
+                b.t[k] = tnow[i];
+                b.nparts[k] = from_transpose ? sims[i]->host_dev.nparts : 1;
+            }
+            EventPair *p;
+            prof_begin(lead, K_FIELD, &p);
+            fn(b, 0, lead->stream);
+            prof_end(lead, p);
+            int rc = check_launch();
+            if (rc != VOG_OK) return rc;
+        }
+    }
+    return VOG_OK;
+}
+
+int run_rho_v(vog_sim *lead, const std::vector<vog_sim *> &sims) {
+    std::map<int, Group> groups;
+    for (vog_sim *s : sims) groups[(int)s->fp64].sims.push_back(s);
+    for (auto &kv : groups) {
+        int rc = for_chunks(kv.second, [&](const Batch &b, size_t base) {
+            int maxnx = 0;
+            for (int k = 0; k < b.n; ++k) maxnx = std::max(maxnx, kv.second.sims[base + k]->cfg.nx);
+            launch_rho_v(kv.first != 0, b, maxnx, lead->stream);
+            return check_launch();
+        });
+        if (rc != VOG_OK) return rc;
+    }
+    return VOG_OK;
+}
+
+int run_moments(vog_sim *lead, const std::vector<vog_sim *> &sims, const std::vector<int64_t> &stepno) {
+    std::map<int, std::vector<size_t>> groups;
+    for (size_t k = 0; k < sims.size(); ++k) groups[(int)sims[k]->fp64].push_back(k);
+    for (auto &kv : groups) {
+        const auto &idx = kv.second;
+        for (size_t base = 0; base < idx.size(); base += kMaxBatch) {
+            Batch b{};
+            b.n = (int)std::min<size_t>(kMaxBatch, idx.size() - base);
+            int maxnx = 0;
+            for (int k = 0; k < b.n; ++k) {
+                const size_t i = idx[base + k];
+                b.s[k] = sims[i]->dev;
+                b.step[k] = stepno[i];
+                maxnx = std::max(maxnx, sims[i]->cfg.nx);
+            }
+            EventPair *p;
+            prof_begin(lead, K_MOMENTS, &p);
+            launch_moments(kv.first != 0, b, maxnx, lead->stream);
+            prof_end(lead, p);
+            int rc = check_launch();
+            if (rc != VOG_OK) return rc;
+        }
+    }
+    return VOG_OK;
+}
+
+// Recompute E from the current f (v layout) and write a record for the
+// current step number.
+int field_from_f(vog_sim *s) {
+    std::vector<vog_sim *> one{s};
+    int rc = run_rho_v(s, one);
+    if (rc != VOG_OK) return rc;
+    std::vector<int64_t> st{s->step};
+    std::vector<double> tt{s->t};
+    return run_field(s, one, st, tt, false);
+}
+
+int device_guard(vog_sim *s) {
+    int cur = -1;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != s->device) HIP_TRY(hipSetDevice(s->device));
+    return VOG_OK;
+}
+
+int step_sims(const std::vector<vog_sim *> &sims, const std::vector<double> &dt, int nsteps) {
+    vog_sim *lead = sims[0];
+    std::vector<double> tau(sims.size());
+    for (size_t k = 0; k < sims.size(); ++k) tau[k] = 0.5 * dt[k];
+    std::vector<int64_t> stepno(sims.size());
+    std::vector<double> tnow(sims.size());
+    for (int n = 0; n < nsteps; ++n) {
+        for (size_t k = 0; k < sims.size(); ++k) {
+            stepno[k] = sims[k]->step + 1;
+            tnow[k] = sims[k]->t + dt[k];
+        }
+        int rc;
+        if ((rc = run_sweep(lead, sims, tau, true)) != VOG_OK) return rc;
+        if ((rc = run_transpose(lead, sims, false)) != VOG_OK) return rc;
+        if ((rc = run_sweep(lead, sims, dt, false)) != VOG_OK) return rc;
+        if ((rc = run_transpose(lead, sims, true)) != VOG_OK) return rc;
+        if ((rc = run_field(lead, sims, stepno, tnow, true)) != VOG_OK) return rc;
+        if ((rc = run_sweep(lead, sims, tau, true)) != VOG_OK) return rc;
+        std::vector<vog_sim *> msims;
+        std::vector<int64_t> mstep;
+        for (size_t k = 0; k < sims.size(); ++k) {
+            const int every = sims[k]->cfg.moments_every;
+            if (every > 0 && stepno[k] % every == 0) {
+                msims.push_back(sims[k]);
+                mstep.push_back(stepno[k]);
+            }
+        }
+        if (!msims.empty() && (rc = run_moments(lead, msims, mstep)) != VOG_OK) return rc;
+        for (size_t k = 0; k < sims.size(); ++k) {
+            sims[k]->step = stepno[k];
+            sims[k]->t = tnow[k];
+        }
+    }
+    return VOG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void vog_config_default(vog_config *c) {
+    if (!c) return;
+    memset(c, 0, sizeof(*c));
+    c->nx = 64;
+    c->nv = 128;
+    c->L = 4.0 * M_PI;
+    c->vmin = -6.0;
+    c->vmax = 6.0;
+    c->degree = 17;
+    c->precision = VOG_FP64_PLAIN;
+    c->poisson = VOG_POISSON_FOURIER;
+    c->field = VOG_FIELD_SELF_CONSISTENT;
+    c->n_feq = 1;
+    c->feq_a[0] = 1.0 / sqrt(2.0 * M_PI);
+    c->feq_c[0] = 0.0;
+    c->feq_sigma[0] = 1.0;
+    c->moments_every = 0;
+}
+
+int vog_config_validate(const vog_config *c) { return validate(c); }
+
+size_t vog_workspace_bytes(const vog_config *c) {
+    if (validate(c) != VOG_OK) return 0;
+    return layout_of(*c).total;
+}
+
+int vog_create(const vog_config *c, void *dev_workspace, size_t bytes, void *hip_stream, vog_sim **out) {
+    if (!out) return fail(VOG_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate(c);
+    if (rc != VOG_OK) return rc;
+    const Layout L = layout_of(*c);
+    if (dev_workspace) {
+        if (bytes < L.total) return fail(VOG_ENOMEM, "workspace smaller than vog_workspace_bytes");
+        if (((uintptr_t)dev_workspace & 255u) != 0) return fail(VOG_EINVAL, "workspace must be 256-byte aligned");
+    }
+    vog_sim *s = new (std::nothrow) vog_sim();
+    if (!s) return fail(VOG_ENOMEM, "host allocation failed");
+    s->cfg = *c;
+    s->lay = L;
+    s->stream = (hipStream_t)hip_stream;
+    s->fp64 = c->precision != VOG_FP32_DELTAF;
+    s->step = 0;
+    s->t = 0.0;
+    s->diag_read = 0;
+    s->prof = false;
+    for (int k = 0; k < VOG_NUM_KINDS; ++k) {
+        s->ev_used[k] = 0;
+        s->ms[k] = 0.0;
+        s->launches[k] = 0;
+    }
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        delete s;
+        return fail(VOG_EDEVICE, "hipGetDevice failed");
+    }
+    if (dev_workspace) {
+        s->ws = (char *)dev_workspace;
+        s->owns = false;
+    } else {
+        void *p = nullptr;
+        if (hipMalloc(&p, L.total) != hipSuccess) {
+            (void)hipGetLastError();
+            delete s;
+            return fail(VOG_ENOMEM, "hipMalloc of the workspace failed");
+        }
+        s->ws = (char *)p;
+        s->owns = true;
+    }
+
+    const bool fp64 = s->fp64;
+    const int nx = c->nx, nv = c->nv;
+    const double dv = (c->vmax - c->vmin) / nv;
+    SimDev &D = s->host_dev;
+    memset(&D, 0, sizeof(D));
+    D.f = s->ws + L.f;
+    D.g = s->ws + L.g;
+    D.E = (double *)(s->ws + L.E);
+    D.part = (double *)(s->ws + L.part);
+    D.mom = (double *)(s->ws + L.mom);
+    D.tab_x = s->ws + L.tab_x;
+    D.tab_v = s->ws + L.tab_v;
+    D.tab_x64 = (const double *)(s->ws + L.tab_x64);
+    D.feq_g = s->ws + L.feq_g;
+    D.feq64 = (const double *)(s->ws + L.feq64);
+    D.ring = (vog_diag *)(s->ws + L.ring);
+    D.nx = nx;
+    D.nv = nv;
+    D.d = (c->degree - 1) / 2;
+    D.deltaf = c->precision != VOG_FP64_PLAIN;
+    D.field_zero = c->field == VOG_FIELD_ZERO;
+    D.n_feq = c->n_feq;
+    D.nparts = (nv + kTile - 1) / kTile;
+    D.fp64 = fp64;
+    D.L = c->L;
+    D.vmin = c->vmin;
+    D.dx = c->L / nx;
+    D.dv = dv;
+    D.inv_dx = nx / c->L;
+    D.inv_dv = 1.0 / dv;
+    for (int g = 0; g < VOG_MAX_FEQ; ++g) {
+        D.feq_c[g] = g < c->n_feq ? c->feq_c[g] : 0.0;
+        D.feq_inv_s2[g] = g < c->n_feq ? 1.0 / (c->feq_sigma[g] * c->feq_sigma[g]) : 0.0;
+    }
+    s->feq64.resize(nv);
+    double feq_sum = 0.0;
+    for (int j = 0; j < nv; ++j) {
+        s->feq64[j] = feq_at(*c, c->vmin + j * dv);
+        feq_sum += s->feq64[j];
+    }
+    D.feq_const = D.deltaf ? dv * feq_sum : 0.0;
+    s->dev = (const SimDev *)(s->ws + L.dev);
+
+    // Host tables (FP64, rounded to the storage precision).
+    std::vector<double> tx64 = interleave_roots<double>(nx);
+    std::vector<double> fg64((size_t)VOG_MAX_FEQ * nv, 0.0);
+    for (int g = 0; g < c->n_feq; ++g)
+        for (int j = 0; j < nv; ++j) {
+            const double z = (c->vmin + j * dv - c->feq_c[g]) / c->feq_sigma[g];
+            fg64[(size_t)g * nv + j] = c->feq_a[g] * exp(-0.5 * z * z);
+        }
+
+    auto bail = [&](int code) {
+        vog_destroy(s);
+        return code;
+    };
+    launch_fill(s->ws, L.total, s->stream);
+    if ((rc = check_launch()) != VOG_OK) return bail(rc);
+    std::vector<char> keep;  // host staging kept alive until the final sync
+    if (fp64) {
+        std::vector<double> tv = interleave_roots<double>(nv);
+        if ((rc = upload(s->ws + L.tab_x, tx64.data(), tx64.size() * 8, s->stream)) != VOG_OK) return bail(rc);
+        if ((rc = upload(s->ws + L.tab_v, tv.data(), tv.size() * 8, s->stream)) != VOG_OK) return bail(rc);
+        if ((rc = upload(s->ws + L.feq_g, fg64.data(), fg64.size() * 8, s->stream)) != VOG_OK) return bail(rc);
+        if ((rc = upload(s->ws + L.tab_x64, tx64.data(), tx64.size() * 8, s->stream)) != VOG_OK) return bail(rc);
+        if ((rc = upload(s->ws + L.feq64, s->feq64.data(), nv * 8, s->stream)) != VOG_OK) return bail(rc);
+        if ((rc = upload(s->ws + L.dev, &D, sizeof(D), s->stream)) != VOG_OK) return bail(rc);
+        if (hipStreamSynchronize(s->stream) != hipSuccess) return bail(fail(VOG_EDEVICE, "sync failed"));
+    } else {
+        std::vector<float> tx = interleave_roots<float>(nx);
+        std::vector<float> tv = interleave_roots<float>(nv);
+        std::vector<float> fg(fg64.begin(), fg64.end());
+        if ((rc = upload(s->ws + L.tab_x, tx.data(), tx.size() * 4, s->stream)) != VOG_OK) return bail(rc);
+        if ((rc = upload(s->ws + L.tab_v, tv.data(), tv.size() * 4, s->stream)) != VOG_OK) return bail(rc);
+        if ((rc = upload(s->ws + L.feq_g, fg.data(), fg.size() * 4, s->stream)) != VOG_OK) return bail(rc);
+        if ((rc = upload(s->ws + L.tab_x64, tx64.data(), tx64.size() * 8, s->stream)) != VOG_OK) return bail(rc);
+        if ((rc = upload(s->ws + L.feq64, s->feq64.data(), nv * 8, s->stream)) != VOG_OK) return bail(rc);
+        if ((rc = upload(s->ws + L.dev, &D, sizeof(D), s->stream)) != VOG_OK) return bail(rc);
+        if (hipStreamSynchronize(s->stream) != hipSuccess) return bail(fail(VOG_EDEVICE, "sync failed"));
+    }
+    *out = s;
+    return VOG_OK;
+}
+
+int vog_init_perturbed(vog_sim *s, int nmodes, const double *amp, const double *kx, const double *phase) {
+    if (!s) return fail(VOG_EINVAL, "sim is NULL");
+    if (nmodes < 0 || nmodes > 8) return fail(VOG_EINVAL, "nmodes must be in [0, 8]");
+    if (nmodes > 0 && (!amp || !kx || !phase)) return fail(VOG_EINVAL, "mode arrays are NULL");
+    for (int m = 0; m < nmodes; ++m)
+        if (!isfinite(amp[m]) || !isfinite(kx[m]) || !isfinite(phase[m]))
+            return fail(VOG_EINVAL, "mode parameters must be finite");
+    int rc = device_guard(s);
+    if (rc != VOG_OK) return rc;
+    launch_init(s->fp64, s->dev, s->cfg.nx * s->cfg.nv, nmodes, amp, kx, phase, s->stream);
+    if ((rc = check_launch()) != VOG_OK) return rc;
+    s->step = 0;
+    s->t = 0.0;
+    s->diag_read = 0;
+    launch_fill(s->host_dev.ring, sizeof(vog_diag) * kRingCap, s->stream);
+    return field_from_f(s);
+}
+
+int vog_set_f(vog_sim *s, const double *host_f) {
+    if (!s || !host_f) return fail(VOG_EINVAL, "NULL argument");
+    int rc = device_guard(s);
+    if (rc != VOG_OK) return rc;
+    const int nx = s->cfg.nx, nv = s->cfg.nv;
+    const size_t cells = (size_t)nx * nv;
+    const bool df = s->host_dev.deltaf;
+    if (s->fp64) {
+        std::vector<double> buf(cells);
+        for (size_t k = 0; k < cells; ++k) buf[k] = host_f[k] - (df ? s->feq64[k % nv] : 0.0);
+        HIP_TRY(hipMemcpyAsync(s->host_dev.f, buf.data(), cells * 8, hipMemcpyHostToDevice, s->stream));
+        HIP_TRY(hipStreamSynchronize(s->stream));
+    } else {
+        std::vector<float> buf(cells);
+        for (size_t k = 0; k < cells; ++k) buf[k] = (float)(host_f[k] - (df ? s->feq64[k % nv] : 0.0));
+        HIP_TRY(hipMemcpyAsync(s->host_dev.f, buf.data(), cells * 4, hipMemcpyHostToDevice, s->stream));
+        HIP_TRY(hipStreamSynchronize(s->stream));
+    }
+    s->step = 0;
+    s->t = 0.0;
+    s->diag_read = 0;
+    launch_fill(s->host_dev.ring, sizeof(vog_diag) * kRingCap, s->stream);
+    return field_from_f(s);
+}
+
+int vog_get_raw(vog_sim *s, void *host_buf, size_t bytes, int *elem_bytes) {
+    if (!s || !host_buf) return fail(VOG_EINVAL, "NULL argument");
+    const size_t es = s->fp64 ? 8 : 4;
+    const size_t need = (size_t)s->cfg.nx * s->cfg.nv * es;
+    if (bytes < need) return fail(VOG_EINVAL, "host buffer too small");
+    int rc = device_guard(s);
+    if (rc != VOG_OK) return rc;
+    HIP_TRY(hipMemcpyAsync(host_buf, s->host_dev.f, need, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    if (elem_bytes) *elem_bytes = (int)es;
+    return VOG_OK;
+}
+
+int vog_get_f(vog_sim *s, double *host_f) {
+    if (!s || !host_f) return fail(VOG_EINVAL, "NULL argument");
+    const int nx = s->cfg.nx, nv = s->cfg.nv;
+    const size_t cells = (size_t)nx * nv;
+    const bool df = s->host_dev.deltaf;
+    int rc;
+    if (s->fp64) {
+        if ((rc = vog_get_raw(s, host_f, cells * 8, nullptr)) != VOG_OK) return rc;
+        if (df)
+            for (size_t k = 0; k < cells; ++k) host_f[k] += s->feq64[k % nv];
+    } else {
+        std::vector<float> buf(cells);
+        if ((rc = vog_get_raw(s, buf.data(), cells * 4, nullptr)) != VOG_OK) return rc;
+        for (size_t k = 0; k < cells; ++k) host_f[k] = (double)buf[k] + (df ? s->feq64[k % nv] : 0.0);
+    }
+    return VOG_OK;
+}
+
+int vog_get_E(vog_sim *s, double *host_E) {
+    if (!s || !host_E) return fail(VOG_EINVAL, "NULL argument");
+    int rc = device_guard(s);
+    if (rc != VOG_OK) return rc;
+    HIP_TRY(hipMemcpyAsync(host_E, s->host_dev.E, sizeof(double) * s->cfg.nx, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return VOG_OK;
+}
+
+int vog_set_E(vog_sim *s, const double *host_E) {
+    if (!s || !host_E) return fail(VOG_EINVAL, "NULL argument");
+    int rc = device_guard(s);
+    if (rc != VOG_OK) return rc;
+    HIP_TRY(hipMemcpyAsync(s->host_dev.E, host_E, sizeof(double) * s->cfg.nx, hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return VOG_OK;
+}
+
+int vog_step(vog_sim *s, double dt, int nsteps) {
+    if (!s) return fail(VOG_EINVAL, "sim is NULL");
+    return vog_step_batch(&s, 1, &dt, nsteps);
+}
+
+int vog_step_batch(vog_sim *const *sims, int nsims, const double *dt, int nsteps) {
+    if (!sims || nsims <= 0 || !dt) return fail(VOG_EINVAL, "empty batch");
+    if (nsteps < 0) return fail(VOG_EINVAL, "nsteps must be >= 0");
+    std::vector<vog_sim *> v(sims, sims + nsims);
+    std::vector<double> d(dt, dt + nsims);
+    for (int k = 0; k < nsims; ++k) {
+        if (!v[k]) return fail(VOG_EINVAL, "NULL sim in batch");
+        if (!(d[k] > 0.0) || !isfinite(d[k])) return fail(VOG_EINVAL, "dt must be finite and > 0");
+        if (v[k]->stream != v[0]->stream || v[k]->device != v[0]->device)
+            return fail(VOG_EINVAL, "all sims of a batch must share the stream and device of sims[0]");
+    }
+    std::vector<vog_sim *> sorted = v;
+    std::sort(sorted.begin(), sorted.end());
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+        return fail(VOG_EINVAL, "a sim appears twice in the batch");
+    if (nsteps == 0) return VOG_OK;
+    int rc = device_guard(v[0]);
+    if (rc != VOG_OK) return rc;
+    return step_sims(v, d, nsteps);
+}
+
+int vog_sweep(vog_sim *s, int which, double arg) {
+    if (!s) return fail(VOG_EINVAL, "sim is NULL");
+    if (which < 0 || which > 2) return fail(VOG_EINVAL, "which must be 0, 1 or 2");
+    if (which < 2 && !isfinite(arg)) return fail(VOG_EINVAL, "arg must be finite");
+    int rc = device_guard(s);
+    if (rc != VOG_OK) return rc;
+    std::vector<vog_sim *> one{s};
+    std::vector<double> a{arg};
+    if (which == 0) return run_sweep(s, one, a, true);
+    if (which == 1) {
+        if ((rc = run_transpose(s, one, false)) != VOG_OK) return rc;
+        if ((rc = run_sweep(s, one, a, false)) != VOG_OK) return rc;
+        return run_transpose(s, one, true);
+    }
+    return field_from_f(s);
+}
+
+int vog_get_diag(vog_sim *s, vog_diag *out, int cap, int *n) {
+    if (!s || !n || (cap > 0 && !out)) return fail(VOG_EINVAL, "NULL argument");
+    *n = 0;
+    int rc = device_guard(s);
+    if (rc != VOG_OK) return rc;
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    const int64_t first = std::max(s->diag_read, s->step - (int64_t)kRingCap + 1);
+    int64_t count = s->step - first + 1;
+    if (count <= 0) return VOG_OK;
+    if (count > cap) count = cap;
+    std::vector<vog_diag> ring(kRingCap);
+    HIP_TRY(hipMemcpy(ring.data(), s->host_dev.ring, sizeof(vog_diag) * kRingCap, hipMemcpyDeviceToHost));
+    for (int64_t k = 0; k < count; ++k) out[k] = ring[(first + k) % kRingCap];
+    *n = (int)count;
+    s->diag_read = first + count;
+    return VOG_OK;
+}
+
+size_t vog_state_bytes(const vog_sim *s) {
+    if (!s) return 0;
+    const size_t es = s->fp64 ? 8 : 4;
+    return 16 + (size_t)s->cfg.nx * s->cfg.nv * es + sizeof(double) * s->cfg.nx;
+}
+
+int vog_get_state(vog_sim *s, void *host_buf, size_t bytes) {
+    if (!s || !host_buf) return fail(VOG_EINVAL, "NULL argument");
+    if (bytes < vog_state_bytes(s)) return fail(VOG_EINVAL, "buffer smaller than vog_state_bytes");
+    int rc = device_guard(s);
+    if (rc != VOG_OK) return rc;
+    const size_t fb = (size_t)s->cfg.nx * s->cfg.nv * (s->fp64 ? 8 : 4);
+    char *p = (char *)host_buf;
+    memcpy(p, &s->step, 8);
+    memcpy(p + 8, &s->t, 8);
+    HIP_TRY(hipMemcpyAsync(p + 16, s->host_dev.f, fb, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipMemcpyAsync(p + 16 + fb, s->host_dev.E, sizeof(double) * s->cfg.nx, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return VOG_OK;
+}
+
+int vog_set_state(vog_sim *s, const void *host_buf, size_t bytes) {
+    if (!s || !host_buf) return fail(VOG_EINVAL, "NULL argument");
+    if (bytes < vog_state_bytes(s)) return fail(VOG_EINVAL, "buffer smaller than vog_state_bytes");
+    int rc = device_guard(s);
+    if (rc != VOG_OK) return rc;
+    const size_t fb = (size_t)s->cfg.nx * s->cfg.nv * (s->fp64 ? 8 : 4);
+    const char *p = (const char *)host_buf;
+    int64_t st;
+    double tt;
+    memcpy(&st, p, 8);
+    memcpy(&tt, p + 8, 8);
+    if (st < 0 || !isfinite(tt)) return fail(VOG_EINVAL, "corrupt state header");
+    HIP_TRY(hipMemcpyAsync(s->host_dev.f, p + 16, fb, hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipMemcpyAsync(s->host_dev.E, p + 16 + fb, sizeof(double) * s->cfg.nx, hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    s->step = st;
+    s->t = tt;
+    s->diag_read = st + 1;
+    return VOG_OK;
+}
+
+int vog_get_time(const vog_sim *s, int64_t *step, double *t) {
+    if (!s) return fail(VOG_EINVAL, "sim is NULL");
+    if (step) *step = s->step;
+    if (t) *t = s->t;
+    return VOG_OK;
+}
+
+int vog_sync(vog_sim *s) {
+    if (!s) return fail(VOG_EINVAL, "sim is NULL");
+    int rc = device_guard(s);
+    if (rc != VOG_OK) return rc;
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    if (s->step > 0 && s->host_dev.field_zero == 0) {
+        vog_diag d;
+        HIP_TRY(hipMemcpy(&d, s->host_dev.ring + (s->step % kRingCap), sizeof(d), hipMemcpyDeviceToHost));
+        if (d.step == s->step && !d.finite) return fail(VOG_ENONFINITE, "field is not finite");
+    }
+    return VOG_OK;
+}
+
+void vog_destroy(vog_sim *s) {
+    if (!s) return;
+    (void)hipStreamSynchronize(s->stream);
+    for (int k = 0; k < VOG_NUM_KINDS; ++k)
+        for (auto &e : s->ev[k]) {
+            (void)hipEventDestroy(e.a);
+            (void)hipEventDestroy(e.b);
+        }
+    if (s->owns && s->ws) (void)hipFree(s->ws);
+    delete s;
+}
+
+const char *vog_strerror(int code) {
+    switch (code) {
+        case VOG_OK: return "ok";
+        case VOG_EINVAL: return "invalid argument";
+        case VOG_ENOMEM: return "out of memory";
+        case VOG_EDEVICE: return "device error";
+        case VOG_ENONFINITE: return "non-finite field";
+        case VOG_EBUSY: return "busy";
+        default: return "unknown error";
+    }
+}
+
+const char *vog_last_error(void) { return g_last_error.c_str(); }
+
+int vog_profile_enable(vog_sim *s, int on) {
+    if (!s) return fail(VOG_EINVAL, "sim is NULL");
+    if (on) {
+        int rc = collect_profile(s);
+        if (rc != VOG_OK) return rc;
+        for (int k = 0; k < VOG_NUM_KINDS; ++k) {
+            s->ms[k] = 0.0;
+            s->launches[k] = 0;
+        }
+    }
+    s->prof = on != 0;
+    return VOG_OK;
+}
+
+int vog_profile_read(vog_sim *s, double *ms, int64_t *launches, int nkinds) {
+    if (!s) return fail(VOG_EINVAL, "sim is NULL");
+    int rc = collect_profile(s);
+    if (rc != VOG_OK) return rc;
+    for (int k = 0; k < nkinds && k < VOG_NUM_KINDS; ++k) {
+        if (ms) ms[k] = s->ms[k];
+        if (launches) launches[k] = s->launches[k];
+    }
+    return VOG_OK;
+}
+
+const char *vog_build_info(void) {
+    return "libvog gfx950: radix-16 Stockham LDS FFT, paired real lines, integer-shift store, "
+           "separate tiled transposes";
+}
+
+}  // extern "C"

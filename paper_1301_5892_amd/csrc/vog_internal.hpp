@@ -1,0 +1,62 @@
+// Internal structures shared by the host runtime and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/vog.h"
+
+namespace vog {
+
+constexpr int kDMax = 8;                 // Lagrange 2d+1 with d <= 8
+constexpr int kTaps = 2 * kDMax + 2;     // 18 stencil offsets q = -8 .. 9
+constexpr int kMaxBatch = 32;            // sims per grouped launch
+constexpr int kRingCap = 4096;           // diagnostics records kept per sim
+constexpr int kTile = 64;                // transpose tile edge
+
+// Per-sim constants and device pointers, stored in the sim's workspace.
+// Written once at creation; kernels read it through a pointer.
+struct SimDev {
+    void *f;            // [nx][nv]  f or delta f, storage precision (v fastest)
+    void *g;            // [nv][nx]  transposed copy used by the x-sweep
+    double *E;          // [nx]      field at the current time level
+    double *part;       // [nparts][nx] partial velocity sums for rho
+    double *mom;        // [nx][2]   per-line moment sums
+    const void *tab_x;  // [2 nx]    exp(i pi k / nx), storage precision (re, im)
+    const void *tab_v;  // [2 nv]    exp(i pi k / nv)
+    const double *tab_x64;  // [2 nx] FP64 copy for the field solve
+    const void *feq_g;  // [n_feq][nv] component values f_g(v_j), storage precision
+    const double *feq64;    // [nv] f_eq(v_j), FP64
+    vog_diag *ring;     // [kRingCap]
+    int nx, nv, d, deltaf, field_zero, n_feq, nparts, fp64;
+    double L, vmin, dx, dv, inv_dx, inv_dv;
+    double feq_c[VOG_MAX_FEQ], feq_inv_s2[VOG_MAX_FEQ];
+    double feq_const;   // dv * sum_j f_eq(v_j) (delta f), else 0
+};
+
+// Kernel argument of a grouped launch: up to kMaxBatch sims, each with its
+// own scalar argument (dt or tau) and step bookkeeping.
+struct Batch {
+    int n;
+    int pad_;
+    const SimDev *s[kMaxBatch];
+    double a[kMaxBatch];      // tau (v-sweep), dt (x-sweep)
+    double t[kMaxBatch];      // time after the step (field solve)
+    int64_t step[kMaxBatch];  // step number after the step (field solve)
+    int nparts[kMaxBatch];    // number of rho partial rows to sum (field solve)
+};
+
+enum Kind { K_SWEEP_V = 0, K_SWEEP_X = 1, K_T_VX = 2, K_T_XV = 3, K_FIELD = 4, K_MOMENTS = 5 };
+
+// Host-side launchers (defined in kernels.hip).
+using LaunchFn = void (*)(const Batch &, int max_lines, hipStream_t);
+LaunchFn sweep_launcher(bool fp64, int n, bool vsweep);
+void launch_transpose(bool fp64, bool to_v, const Batch &b, int max_tiles, hipStream_t st);
+LaunchFn field_launcher(int nx);
+void launch_rho_v(bool fp64, const Batch &b, int max_nx, hipStream_t st);
+void launch_moments(bool fp64, const Batch &b, int max_nx, hipStream_t st);
+void launch_init(bool fp64, const SimDev *s, int cells, int nmodes, const double *amp,
+                 const double *kx, const double *ph, hipStream_t st);
+void launch_fill(void *p, size_t bytes, hipStream_t st);
+
+}  // namespace vog

@@ -18,3 +18,23 @@ def orc():
     import oracle
     oracle.lib()
     return oracle
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    # Name the case on the real stderr before it touches the GPU, so that a
+    # run that dies still says which case was running.
+    if request.node.get_closest_marker("gpu") is not None:
+        sys.__stderr__.write(f"\n[gpu case] {request.node.nodeid}\n")
+        sys.__stderr__.flush()
+    yield
+
+
+@pytest.fixture(scope="session")
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    from paper_1301_5892_amd import vog
+    vog.load()
+    torch.cuda.init()
+    return vog

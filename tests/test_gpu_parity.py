@@ -1,0 +1,324 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU FP64 oracle.
+
+Tolerances (relative, infinity norm over the compared array):
+  FP64 paths (plain and delta f): 1e-12;
+  FP32 delta f: 1e-5 on delta f (and on E).
+Both sides start from the same seeded inputs (workloads); the oracle computes
+every expected value itself.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+def rel(a, b):
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def sim_of(gpu, w, **kw):
+    return gpu.Sim(w, **kw)
+
+
+def stored(o):
+    """The oracle's stored array (f or delta f)."""
+    return o.f
+
+
+# ---------------------------------------------------------------- single sweeps
+
+SWEEP_GRIDS = [(8, 8, 7), (16, 32, 15), (32, 64, 17), (64, 128, 17), (256, 64, 17),
+               (64, 1024, 17), (128, 4096, 17), (4096, 16, 9), (512, 512, 3), (32, 32, 1)]
+
+
+@pytest.mark.parametrize("nx,nv,deg", SWEEP_GRIDS, ids=lambda x: str(x))
+@pytest.mark.parametrize("dt", [0.1, -0.37, 2.9])
+def test_x_sweep_fp64(gpu, nx, nv, deg, dt):
+    w = workloads.landau_weak().replace(nx=nx, nv=nv, degree=deg, amp=(0.3, 0.1),
+                                         kx=(0.5, 1.5), phase=(0.2, 1.0))
+    s = sim_of(gpu, w).init()
+    o = oracle.Oracle(w).init()
+    s.advect_x(dt)
+    o.advect_x(dt)
+    assert rel(s.get_f(), o.f) < TOL64
+
+
+@pytest.mark.parametrize("nx,nv,deg", SWEEP_GRIDS, ids=lambda x: str(x))
+@pytest.mark.parametrize("precision", ["fp64_plain", "fp64_deltaf"])
+def test_v_sweep_fp64(gpu, nx, nv, deg, precision):
+    w = workloads.landau_weak().replace(nx=nx, nv=nv, degree=deg, precision=precision,
+                                         amp=(0.2,), kx=(0.5,), phase=(0.0,))
+    rng = np.random.default_rng(nx * 7 + nv)
+    E = rng.uniform(-3.0, 3.0, nx)        # shifts of several cells either way
+    s = sim_of(gpu, w).init()
+    o = oracle.Oracle(w).init()
+    s.set_E(E)
+    s.advect_v(0.35)
+    o.advect_v(0.35, E)
+    assert rel(s.get_raw(), stored(o)) < TOL64
+
+
+@pytest.mark.parametrize("nx,nv", [(64, 128), (256, 512), (32, 4096), (1024, 64)])
+def test_v_sweep_fp32_deltaf(gpu, nx, nv):
+    w = workloads.landau_strong().replace(nx=nx, nv=nv)
+    rng = np.random.default_rng(5)
+    E = rng.uniform(-1.5, 1.5, nx)
+    s = sim_of(gpu, w).init()
+    o = oracle.Oracle(w).init()
+    s.set_E(E)
+    s.advect_v(0.25)
+    o.advect_v(0.25, E)
+    assert rel(s.get_raw(), o.f) < TOL32
+
+
+@pytest.mark.parametrize("n,deg", [(8, 1), (8, 3), (16, 9), (32, 17), (64, 17)])
+def test_fft_sweep_equals_dense_circulant(gpu, n, deg):
+    # The x-advection of each v-row equals the dense product A u with
+    # A = C(a_0 .. a_{n-1}) built from the paper's first-row definition.
+    nv = 32
+    w = workloads.landau_weak().replace(nx=n, nv=nv, degree=deg)
+    rng = np.random.default_rng(n + deg)
+    f = rng.standard_normal((n, nv))
+    s = sim_of(gpu, w)
+    s.set_f(f)
+    dt = 0.77
+    s.advect_x(dt)
+    out = s.get_f()
+    o = oracle.Oracle(w)
+    dx, dv = w.L / n, (w.vmax - w.vmin) / nv
+    exp = np.zeros_like(f)
+    for j in range(nv):
+        beta = -(w.vmin + j * dv) * dt / dx
+        a = oracle.circulant_row(n, (deg - 1) // 2, beta)
+        A = np.array([[a[(k - i) % n] for k in range(n)] for i in range(n)])
+        exp[:, j] = A @ f[:, j]
+    assert np.max(np.abs(out - exp)) < 1e-13 * max(1.0, np.max(np.abs(f)))
+
+
+def test_integer_shift_is_a_roll(gpu):
+    # dt chosen so that every v_j dt / dx is an integer: the sweep is an exact
+    # cyclic roll of each row (up to FFT rounding of the identity kernel).
+    nx, nv = 64, 32
+    w = workloads.landau_weak().replace(nx=nx, nv=nv, vmin=-4.0, vmax=4.0, L=4.0 * math.pi)
+    dx, dv = w.L / nx, 8.0 / nv
+    dt = dx / dv           # beta_j = -(vmin + j dv) / dv, an integer
+    rng = np.random.default_rng(3)
+    f = rng.standard_normal((nx, nv))
+    s = sim_of(gpu, w)
+    s.set_f(f)
+    s.advect_x(dt)
+    out = s.get_f()
+    for j in range(nv):
+        beta = int(round(-(w.vmin + j * dv) * dt / dx))
+        assert np.max(np.abs(out[:, j] - np.roll(f[:, j], -beta))) < 1e-14
+
+
+def test_zero_field_v_sweep_is_identity(gpu):
+    w = workloads.landau_weak().replace(precision="fp32_deltaf")
+    s = sim_of(gpu, w).init()
+    before = s.get_raw().copy()
+    s.set_E(np.zeros(w.nx))
+    s.advect_v(0.05)
+    assert np.max(np.abs(s.get_raw() - before)) <= 1e-6 * np.max(np.abs(before))
+
+
+# ---------------------------------------------------------------- field solve
+
+@pytest.mark.parametrize("nx,nv", [(8, 16), (64, 128), (256, 512), (4096, 64), (1024, 2048)])
+def test_field_fp64(gpu, nx, nv):
+    deg = min(17, min(nx, nv) - 1)
+    w = workloads.landau_weak().replace(nx=nx, nv=nv, degree=deg, amp=(0.1, 0.02),
+                                         kx=(0.5, 2.0), phase=(0.0, 0.7))
+    s = sim_of(gpu, w).init()
+    o = oracle.Oracle(w).init()
+    assert rel(s.get_E(), o.E) < TOL64
+    d = s.diag()
+    assert d.size == 1 and d["step"][0] == 0
+    ref = o.diag_field()
+    assert abs(d["normE"][0] - ref[0]) <= 1e-12 * ref[0]
+    assert abs(d["rho0"][0] - ref[1]) <= 1e-13
+    assert abs(d["abs_rho1"][0] - ref[2]) <= 1e-12 * max(ref[2], 1e-3)
+
+
+def test_field_closed_form(gpu):
+    # f = (1 + a cos(k x)) f_M: E = (a / k) sin(k x) up to the Maxwellian tail.
+    w = workloads.landau_weak().replace(nx=128, nv=256, vmin=-10.0, vmax=10.0)
+    s = sim_of(gpu, w).init()
+    x = np.arange(w.nx) * w.L / w.nx
+    assert np.max(np.abs(s.get_E() - 0.01 / 0.5 * np.sin(0.5 * x))) < 1e-14
+
+
+# ---------------------------------------------------------------- full steps
+
+def test_landau_weak_fp64_full_run(gpu):
+    w = workloads.landau_weak()
+    s = sim_of(gpu, w).init()
+    o = oracle.Oracle(w).init()
+    s.step(w.nsteps)
+    od = o.step(w.nsteps)
+    assert rel(s.get_f(), o.f) < TOL64
+    assert rel(s.get_E(), o.E) < 1e-11
+    d = s.diag()
+    assert d.size == w.nsteps + 1
+    assert np.all(d["finite"] == 1)
+    assert np.max(np.abs(d["normE"][1:] - od[:, 0]) / od[:, 0]) < 1e-10
+    t = d["t"][1:]
+    gamma, omega, _ = oracle.landau_fit(t, d["normE"][1:])
+    assert abs(-gamma - 0.1533) / 0.1533 < 0.05
+    assert abs(omega - 1.4156) / 1.4156 < 0.01
+
+
+def test_landau_long_rate_gpu(gpu):
+    w = workloads.landau_long()
+    s = sim_of(gpu, w).init()
+    s.step(w.nsteps)
+    d = s.diag()
+    gamma, omega, _ = oracle.landau_fit(d["t"][1:], d["normE"][1:], 4.0, 36.0)
+    assert abs(-gamma - 0.1533) / 0.1533 < 0.02
+    assert abs(omega - 1.4156) / 1.4156 < 0.005
+
+
+@pytest.mark.parametrize("precision", ["fp64_plain", "fp64_deltaf", "fp32_deltaf"])
+def test_free_streaming(gpu, precision):
+    w = workloads.free_streaming(64, 64, 20).replace(precision=precision)
+    s = sim_of(gpu, w).init()
+    s.step(w.nsteps)
+    f = s.get_f()
+    x = (np.arange(w.nx) * w.L / w.nx)[:, None]
+    v = (w.vmin + np.arange(w.nv) * (w.vmax - w.vmin) / w.nv)[None, :]
+    t = w.nsteps * w.dt
+    fm = np.exp(-v ** 2 / 2) / math.sqrt(2 * math.pi)
+    exact = (1 + 0.05 * np.cos(0.5 * (x - v * t) + 0.3)) * fm
+    tol = 1e-13 if precision != "fp32_deltaf" else 2e-7
+    assert np.max(np.abs(f - exact)) < tol
+    assert np.max(np.abs(s.get_E())) == 0.0
+
+
+def test_landau_fp64_deltaf_matches_oracle(gpu):
+    w = workloads.landau_weak().replace(precision="fp64_deltaf")
+    s = sim_of(gpu, w).init()
+    o = oracle.Oracle(w).init()
+    s.step(30)
+    o.step(30)
+    assert rel(s.get_raw(), o.f) < TOL64
+    assert rel(s.get_E(), o.E) < 1e-11
+
+
+@pytest.mark.parametrize("nsteps", [1, 10])
+def test_landau_strong_fp32_deltaf(gpu, nsteps):
+    w = workloads.landau_strong()
+    s = sim_of(gpu, w).init()
+    o = oracle.Oracle(w).init()
+    s.step(nsteps)
+    o.step(nsteps)
+    assert rel(s.get_raw(), o.f) < TOL32
+    assert rel(s.get_E(), o.E) < TOL32
+
+
+@pytest.mark.parametrize("nsteps", [1, 10])
+def test_landau_strong_fp64_plain(gpu, nsteps):
+    w = workloads.landau_strong().replace(precision="fp64_plain")
+    s = sim_of(gpu, w).init()
+    o = oracle.Oracle(w).init()
+    s.step(nsteps)
+    o.step(nsteps)
+    assert rel(s.get_f(), o.f) < TOL64
+
+
+@pytest.mark.parametrize("nsteps", [1, 10])
+def test_bump_on_tail_fp32_deltaf(gpu, nsteps):
+    w = workloads.bump_on_tail()
+    s = sim_of(gpu, w).init()
+    o = oracle.Oracle(w).init()
+    s.step(nsteps)
+    o.step(nsteps)
+    assert rel(s.get_raw(), o.f) < TOL32
+    assert rel(s.get_E(), o.E) < TOL32
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32_deltaf", TOL32), ("fp64_plain", TOL64)])
+def test_large_grid_full_size(gpu, precision, tol):
+    w = workloads.large_grid().replace(precision=precision)
+    s = sim_of(gpu, w).init()
+    o = oracle.Oracle(w).init()
+    s.step(2)
+    o.step(2)
+    got = s.get_raw() if precision == "fp32_deltaf" else s.get_f()
+    assert rel(got, o.f) < tol
+    assert rel(s.get_E(), o.E) < max(tol, 1e-11)
+
+
+# ---------------------------------------------------------------- runtime behaviour
+
+def test_batch_equals_alone_bitwise(gpu):
+    ws = [workloads.landau_weak().replace(precision="fp32_deltaf"),
+          workloads.landau_strong(),
+          workloads.landau_weak().replace(nx=32, nv=512, precision="fp32_deltaf"),
+          workloads.landau_weak().replace(nx=128, nv=128),
+          workloads.landau_strong().replace(nx=256, nv=512, amp=(0.05,))]
+    alone = []
+    for w in ws:
+        s = sim_of(gpu, w).init()
+        s.step(7)
+        alone.append((s.get_raw(), s.get_E()))
+    mix = [sim_of(gpu, w).init() for w in ws]
+    gpu.step_batch(mix, 7)
+    for (f0, e0), s in zip(alone, mix):
+        assert np.array_equal(s.get_raw(), f0)
+        assert np.array_equal(s.get_E(), e0)
+
+
+def test_checkpoint_resume_bitwise(gpu):
+    w = workloads.landau_strong()
+    a = sim_of(gpu, w).init()
+    a.step(12)
+    ref = a.get_raw().copy()
+    b = sim_of(gpu, w).init()
+    b.step(5)
+    state = b.get_state()
+    c = sim_of(gpu, w)
+    c.set_state(state)
+    assert c.time()[0] == 5
+    c.step(7)
+    assert np.array_equal(c.get_raw(), ref)
+
+
+def test_deterministic(gpu):
+    w = workloads.bump_on_tail()
+    runs = []
+    for _ in range(2):
+        s = sim_of(gpu, w).init()
+        s.step(3)
+        runs.append(s.get_raw())
+    assert np.array_equal(runs[0], runs[1])
+
+
+def test_moments_match_oracle(gpu):
+    w = workloads.landau_weak().replace(precision="fp64_deltaf")
+    s = sim_of(gpu, w, moments_every=5).init()
+    o = oracle.Oracle(w).init()
+    s.step(10)
+    o.step(10)
+    d = s.diag()
+    last = d[d["step"] == 10][0]
+    ref = o.diag_moments()
+    assert abs(last["l2"] - ref[0]) / ref[0] < 1e-12
+    assert abs(last["energy"] - ref[1]) / ref[1] < 1e-12
+    assert np.isnan(d[d["step"] == 9][0]["l2"])
+
+
+def test_step_rejects_bad_dt(gpu):
+    s = sim_of(gpu, workloads.landau_weak()).init()
+    with pytest.raises(gpu.VogError):
+        s.step(1, dt=float("nan"))
+    with pytest.raises(gpu.VogError):
+        s.step(1, dt=-0.1)
