@@ -34,8 +34,15 @@ __device__ __forceinline__ double lagrange_weight(int d, int q, double s) {
     return num / den;
 }
 
-// beta = b + s with b integer and s in [0, 1).
+// beta = b + s with b integer and s in [0, 1).  A non-finite or absurdly
+// large beta (a diverged field) gives b = 0 and s = NaN, so the line becomes
+// NaN and the failure shows in the field's finite flag.
 __device__ __forceinline__ void split_shift(double beta, long long &b, double &s) {
+    if (!(fabs(beta) < 1e15)) {
+        b = 0;
+        s = __builtin_nan("");
+        return;
+    }
     double fb = floor(beta);
     double r = beta - fb;
     if (r >= 1.0) {

@@ -1,0 +1,269 @@
+"""Continuous-batching request loop for many Vlasov-Poisson simulations.
+
+Requests (a workload each) arrive over time.  The scheduler keeps every
+admitted simulation's f and E resident in device memory, admits waiting
+requests in arrival order whenever a slot is free and the summed device
+footprint (vog_workspace_bytes of each sim) stays within the budget, and
+advances all active simulations together in quanta of Strang steps with
+grouped launches (vog_step_batch: one launch per kernel type and line length
+across the whole active set).  Finished, failed or cancelled simulations are
+retired between quanta, which frees their memory and slot for the next
+admission.  Latency of a request = completion time - arrival time.
+
+The scheduler talks to an executor; `GpuExecutor` drives libvog on the
+current torch stream.  Per-simulation arithmetic does not depend on which
+other simulations share a launch, so each result equals the result of the
+same request run alone.
+"""
+from __future__ import annotations
+
+import dataclasses
+import hashlib
+import math
+import time
+from collections import deque
+from typing import Any, Dict, List, Optional, Sequence
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Outcome:
+    rid: int
+    status: str                 # "done", "failed", "cancelled", "rejected"
+    arrival: float
+    admitted: Optional[float]
+    completed: Optional[float]
+    cell_steps: int
+    result: Any = None
+
+    @property
+    def latency(self) -> Optional[float]:
+        return None if self.completed is None else self.completed - self.arrival
+
+
+@dataclasses.dataclass
+class _Active:
+    req: Any
+    handle: Any
+    remaining: int
+    footprint: int
+    admitted: float
+
+
+class Scheduler:
+    """Admission by memory footprint + quantum-based continuous batching."""
+
+    def __init__(self, executor, budget_bytes: int, max_active: int = 64, quantum: int = 50):
+        if budget_bytes <= 0 or max_active <= 0 or quantum <= 0:
+            raise ValueError("budget, max_active and quantum must be positive")
+        self.ex = executor
+        self.budget = int(budget_bytes)
+        self.max_active = int(max_active)
+        self.quantum = int(quantum)
+        self.cancelled: set = set()
+        self.stats = {"quanta": 0, "max_active": 0, "max_bytes": 0, "max_queue": 0}
+
+    def cancel(self, rid: int) -> None:
+        self.cancelled.add(rid)
+
+    def run(self, requests: Sequence[Any]) -> List[Outcome]:
+        """Serve `requests` (each with .rid, .arrival, .workload), arrival
+        times in seconds relative to the start of the run."""
+        pending = deque(sorted(requests, key=lambda r: (r.arrival, r.rid)))
+        waiting: deque = deque()
+        active: List[_Active] = []
+        outcomes: Dict[int, Outcome] = {}
+        used = 0
+        t0 = self.ex.now()
+
+        def now() -> float:
+            return self.ex.now() - t0
+
+        while pending or waiting or active:
+            tnow = now()
+            while pending and pending[0].arrival <= tnow:
+                waiting.append(pending.popleft())
+            # cancellations of waiting requests
+            if self.cancelled:
+                keep = deque()
+                for r in waiting:
+                    if r.rid in self.cancelled:
+                        outcomes[r.rid] = Outcome(r.rid, "cancelled", r.arrival, None, tnow, 0)
+                    else:
+                        keep.append(r)
+                waiting = keep
+            # admission in arrival order
+            while waiting and len(active) < self.max_active:
+                r = waiting[0]
+                fp = self.ex.footprint(r.workload)
+                if fp > self.budget:
+                    waiting.popleft()
+                    outcomes[r.rid] = Outcome(r.rid, "rejected", r.arrival, None, now(), 0)
+                    continue
+                if used + fp > self.budget:
+                    break
+                waiting.popleft()
+                h = self.ex.start(r)
+                active.append(_Active(r, h, r.workload.nsteps, fp, now()))
+                used += fp
+            self.stats["max_active"] = max(self.stats["max_active"], len(active))
+            self.stats["max_bytes"] = max(self.stats["max_bytes"], used)
+            self.stats["max_queue"] = max(self.stats["max_queue"], len(waiting))
+            if not active:
+                if pending:
+                    self.ex.wait_until(t0 + pending[0].arrival)
+                continue
+            # one quantum for every active sim
+            counts = [min(self.quantum, a.remaining) for a in active]
+            self.ex.advance([a.handle for a in active], counts)
+            self.stats["quanta"] += 1
+            tq = now()
+            still: List[_Active] = []
+            for a, c in zip(active, counts):
+                a.remaining -= c
+                rid = a.req.rid
+                w = a.req.workload
+                if rid in self.cancelled:
+                    status = "cancelled"
+                elif self.ex.failed(a.handle):
+                    status = "failed"
+                elif a.remaining == 0:
+                    status = "done"
+                else:
+                    still.append(a)
+                    continue
+                res = self.ex.finish(a.handle) if status == "done" else None
+                done_steps = w.nsteps - a.remaining
+                outcomes[rid] = Outcome(rid, status, a.req.arrival, a.admitted, tq,
+                                        w.nx * w.nv * done_steps, res)
+                self.ex.release(a.handle)
+                used -= a.footprint
+            active = still
+        return [outcomes[k] for k in sorted(outcomes)]
+
+
+class GpuExecutor:
+    """Runs requests with libvog on the current torch stream."""
+
+    def __init__(self, moments_every: int = 0, keep_state: bool = False):
+        import torch
+
+        from . import vog
+        self.torch = torch
+        self.vog = vog
+        self.moments_every = moments_every
+        self.keep_state = keep_state
+        vog.load()
+
+    def now(self) -> float:
+        return time.perf_counter()
+
+    def wait_until(self, t: float) -> None:
+        dt = t - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+
+    def footprint(self, w) -> int:
+        return self.vog.workspace_bytes(self.vog.make_config(w, self.moments_every))
+
+    def start(self, req):
+        return self.vog.Sim(req.workload, moments_every=self.moments_every).init()
+
+    def advance(self, handles, counts) -> None:
+        groups: Dict[int, list] = {}
+        for h, c in zip(handles, counts):
+            groups.setdefault(c, []).append(h)
+        for c, hs in sorted(groups.items(), reverse=True):
+            self.vog.step_batch(hs, c)
+        self.torch.cuda.synchronize()
+
+    def failed(self, h) -> bool:
+        try:
+            h.sync()
+            return False
+        except self.vog.VogError as e:
+            if e.code == self.vog.ENONFINITE:
+                return True
+            raise
+
+    def finish(self, h):
+        raw = h.get_raw()
+        E = h.get_E()
+        out = {"E": E, "digest": hashlib.sha256(raw.tobytes()).hexdigest(),
+               "step": h.time()[0]}
+        if self.keep_state:
+            out["raw"] = raw
+        return out
+
+    def release(self, h) -> None:
+        h.close()
+        h.workspace = None
+
+
+def summarize(outcomes: Sequence[Outcome]) -> Dict[str, Any]:
+    done = [o for o in outcomes if o.status == "done"]
+    lat = np.array([o.latency for o in done]) if done else np.zeros(0)
+    work = sum(o.cell_steps for o in outcomes)
+    if done:
+        first = min(o.arrival for o in outcomes)
+        last = max(o.completed for o in outcomes if o.completed is not None)
+        span = last - first
+    else:
+        span = float("nan")
+    return {
+        "requests": len(outcomes),
+        "done": len(done),
+        "failed": sum(o.status == "failed" for o in outcomes),
+        "cancelled": sum(o.status == "cancelled" for o in outcomes),
+        "rejected": sum(o.status == "rejected" for o in outcomes),
+        "p50_latency_s": float(np.percentile(lat, 50)) if lat.size else None,
+        "p99_latency_s": float(np.percentile(lat, 99)) if lat.size else None,
+        "mean_latency_s": float(lat.mean()) if lat.size else None,
+        "cell_updates": int(work),
+        "makespan_s": span,
+        "aggregate_cell_updates_per_s": work / span if span and span > 0 else None,
+    }
+
+
+def bench(n_requests: int = 512, load_factor: float = 0.8, quantum: int = 50,
+          max_active: int = 64, budget_bytes: int = 64 << 30, seed: int = 1) -> Dict[str, Any]:
+    """Serving mix: closed-loop capacity pass (all requests present at t=0),
+    then an open-loop pass with Poisson arrivals at load_factor x capacity."""
+    import workloads
+
+    ex = GpuExecutor()
+    # warm the kernels of every line length used by the mix
+    warm = workloads.serving_mix(min(n_requests, 32), rate=1e9, seed=seed,
+                                 steps_range=(2, 2))
+    Scheduler(ex, budget_bytes, max_active, quantum).run(warm)
+
+    reqs0 = workloads.serving_mix(n_requests, rate=1.0, seed=seed)
+    closed = [dataclasses.replace(r, arrival=0.0) for r in reqs0]
+    t0 = time.perf_counter()
+    res_closed = Scheduler(ex, budget_bytes, max_active, quantum).run(closed)
+    cap_time = time.perf_counter() - t0
+    capacity = n_requests / cap_time              # requests per second
+    rate = load_factor * capacity
+    reqs = workloads.serving_mix(n_requests, rate=rate, seed=seed)
+    sched = Scheduler(ex, budget_bytes, max_active, quantum)
+    res_open = sched.run(reqs)
+    s_open = summarize(res_open)
+    s_closed = summarize(res_closed)
+    return {
+        "requests": n_requests,
+        "arrival_rate_per_s": rate,
+        "load_factor": load_factor,
+        "closed_loop_capacity_req_per_s": capacity,
+        "closed_loop_aggregate_cell_updates_per_s": s_closed["aggregate_cell_updates_per_s"],
+        "p50_latency_s": s_open["p50_latency_s"],
+        "p99_latency_s": s_open["p99_latency_s"],
+        "mean_latency_s": s_open["mean_latency_s"],
+        "aggregate_cell_updates_per_s": s_open["aggregate_cell_updates_per_s"],
+        "done": s_open["done"],
+        "failed": s_open["failed"],
+        "quantum_steps": quantum,
+        "max_active": sched.stats["max_active"],
+        "max_queue": sched.stats["max_queue"],
+        "budget_bytes": budget_bytes,
+    }

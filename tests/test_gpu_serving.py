@@ -1,0 +1,65 @@
+"""GPU serving: each request's result is the same alone and in the mix, a
+diverged request fails without touching the others, and the latency summary
+is filled."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def small_mix(n=12):
+    reqs = workloads.serving_mix(n, rate=1e6, seed=7, steps_range=(20, 60),
+                                 nx_pow=(6, 8), nv_pow=(7, 9))
+    return reqs
+
+
+def test_alone_equals_mix_bitwise(gpu):
+    from paper_1301_5892_amd import serving, vog
+    reqs = small_mix()
+    ex = serving.GpuExecutor(keep_state=True)
+    budget = 3 * max(ex.footprint(r.workload) for r in reqs)      # forces queueing
+    sched = serving.Scheduler(ex, budget_bytes=budget, max_active=6, quantum=7)
+    out = sched.run(reqs)
+    assert all(o.status == "done" for o in out)
+    assert sched.stats["max_queue"] > 0 and sched.stats["max_active"] >= 2
+    for o, r in zip(out, sorted(reqs, key=lambda r: r.rid)):
+        s = vog.Sim(r.workload).init()
+        s.step(r.workload.nsteps)
+        assert np.array_equal(s.get_raw(), o.result["raw"]), r.rid
+        assert np.array_equal(s.get_E(), o.result["E"]), r.rid
+        s.close()
+
+
+def test_diverged_request_fails_alone(gpu):
+    from paper_1301_5892_amd import serving
+
+    class NanExecutor(serving.GpuExecutor):
+        def start(self, req):
+            sim = super().start(req)
+            if req.rid == 2:
+                f = sim.get_f()
+                f[3, 5] = float("nan")
+                sim.set_f(f)
+            return sim
+
+    reqs = small_mix(6)
+    ex = NanExecutor()
+    out = serving.Scheduler(ex, budget_bytes=1 << 34, max_active=6, quantum=10).run(reqs)
+    status = {o.rid: o.status for o in out}
+    assert status[2] == "failed"
+    assert all(s == "done" for rid, s in status.items() if rid != 2)
+
+
+def test_serving_summary(gpu):
+    from paper_1301_5892_amd import serving
+    reqs = workloads.serving_mix(16, rate=200.0, seed=11, steps_range=(20, 40))
+    out = serving.Scheduler(serving.GpuExecutor(), budget_bytes=1 << 34, max_active=8,
+                            quantum=10).run(reqs)
+    s = serving.summarize(out)
+    assert s["done"] == 16
+    assert 0 < s["p50_latency_s"] <= s["p99_latency_s"]
+    assert s["aggregate_cell_updates_per_s"] > 0
