@@ -5,15 +5,18 @@
 // registers.  The transform is a Stockham autosort sequence of passes of
 // radix 16 (the last pass takes the remaining factor 2, 4, 8 or 16); every
 // pass works on registers, and consecutive passes exchange data through LDS
-// (structure-of-arrays, one padding slot per 16 elements).
+// (structure-of-arrays, one padding slot per 16 elements, so that every LDS
+// address is a per-thread base plus a compile-time offset).
 //
 // Layouts (t = thread index within the transform, 0 <= t < TPF):
 //   input:  register r holds element t + r * TPF            (r < R)
 //   output: register i holds frequency t + TPF * kpos(i)    (i < R)
 // kpos is a compile-time permutation fixed by the last pass radix.
 //
-// Twiddle factors come from a per-length table tab[k] = exp(+i pi k / N),
-// k < 2N, built in FP64 on the host and rounded to the storage precision.
+// Twiddles of pass p >= 1 (sub-transform length NS = 16^p, radix RP) come
+// from a table with one row of 16 entries per k < NS:
+//   row k, entry r = exp(+2 pi i r k / (NS RP))   (conjugated when forward),
+// built in FP64 on the host and rounded to the storage precision.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -24,7 +27,7 @@
 namespace vog {
 
 template <typename T>
-struct cx {
+struct alignas(2 * sizeof(T)) cx {
     T re, im;
 };
 
@@ -40,8 +43,6 @@ template <typename T>
 __device__ __forceinline__ cx<T> cmul_conj(cx<T> a, cx<T> b) {  // a * conj(b)
     return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
 }
-template <typename T>
-__device__ __forceinline__ cx<T> cscale(cx<T> a, T s) { return {a.re * s, a.im * s}; }
 
 template <int B, int E, typename F>
 __device__ __forceinline__ void static_for(F &&f) {
@@ -53,6 +54,18 @@ __device__ __forceinline__ void static_for(F &&f) {
 
 constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
 constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
+
+// Pass structure shared by the kernels and the host table builder.
+constexpr int fft_regs(int n) { return n < 16 ? n : 16; }
+constexpr int fft_npass(int n) { return (ilog2(n) + 3) / 4; }
+constexpr int fft_radix(int n, int p) {
+    return p == fft_npass(n) - 1 ? n / ipow(16, fft_npass(n) - 1) : 16;
+}
+constexpr int fft_ns(int p) { return ipow(16, p); }
+// Offset (in complex entries) of the twiddle rows of pass p (p >= 1).
+constexpr int fft_tw_off(int n, int p) { return p <= 1 ? 0 : fft_tw_off(n, p - 1) + 16 * fft_ns(p - 1); }
+constexpr int fft_tw_total(int n) { return fft_npass(n) <= 1 ? 16 : fft_tw_off(n, fft_npass(n)); }
+constexpr int kEpsRow = 10;  // entries per thread row of the symbol table (q = 0 .. 9)
 
 // cos(2 pi j / 16), j = 0..15; sin(2 pi j / 16) = cos(2 pi (j - 4) / 16).
 constexpr double kCos16[16] = {
@@ -118,18 +131,36 @@ __device__ __forceinline__ void dft(cx<T> *v) {
     }
 }
 
+// Loads entries [0, n) of a table row (n even, row 16-byte aligned).
+template <typename T, int NE>
+__device__ __forceinline__ void load_row(const cx<T> *__restrict__ row, cx<T> (&out)[NE]) {
+    if constexpr (sizeof(T) == 4) {
+        const float4 *p = reinterpret_cast<const float4 *>(row);
+        static_for<0, NE / 2>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            const float4 q = p[i];
+            out[2 * i] = cx<T>{q.x, q.y};
+            out[2 * i + 1] = cx<T>{q.z, q.w};
+        });
+    } else {
+        static_for<0, NE>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            out[i] = row[i];
+        });
+    }
+}
+
 template <typename T, int N>
 struct Fft {
     static_assert(N >= 8 && N <= 4096 && (N & (N - 1)) == 0, "N must be a power of two in [8, 4096]");
-    static constexpr int R = N < 16 ? N : 16;
+    static constexpr int R = fft_regs(N);
     static constexpr int TPF = N / R;
-    static constexpr int LOG = ilog2(N);
-    static constexpr int NPASS = (LOG + 3) / 4;
-    static constexpr int LAST = N / ipow(16, NPASS - 1);
+    static constexpr int NPASS = fft_npass(N);
+    static constexpr int LAST = fft_radix(N, NPASS - 1);
     static constexpr int LDSN = N + N / 16;  // padded SoA length
 
-    static constexpr int radix(int p) { return p == NPASS - 1 ? LAST : 16; }
-    static constexpr int ns(int p) { return ipow(16, p); }
+    static constexpr int radix(int p) { return fft_radix(N, p); }
+    static constexpr int ns(int p) { return fft_ns(p); }
     // frequency index (in units of TPF, offset t) held by register i after the last pass
     static constexpr int kpos(int i) { return i / LAST + (i % LAST) * (R / LAST); }
     static constexpr int kinv(int k) {  // register index holding position k
@@ -138,22 +169,25 @@ struct Fft {
         return -1;
     }
     static __device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
+    // pad(x + C) given px = pad(x), for a compile-time C that is a multiple of 16
+    // (or any C when the caller knows x + C stays inside x's 16-block).
+    template <int C>
+    static __device__ __forceinline__ int pad_add(int px) { return px + C + C / 16; }
 
     // One radix pass on registers (twiddles, then DFT of each group).
     template <int DIR, int P>
-    static __device__ __forceinline__ void pass(cx<T> (&v)[R], int t, const cx<T> *__restrict__ tab) {
+    static __device__ __forceinline__ void pass(cx<T> (&v)[R], int t, const cx<T> *__restrict__ tw) {
         constexpr int RP = radix(P), NS = ns(P);
         static_for<0, R / RP>([&](auto uc) {
             constexpr int u = decltype(uc)::value;
             if constexpr (NS > 1) {
-                const int jb = t + u * TPF;
-                const int k = jb & (NS - 1);
-                constexpr int SC = 2 * N / (NS * RP);  // table stride: exp(2 pi i r k / (NS RP))
+                const int k = (t + u * TPF) & (NS - 1);
+                cx<T> w[RP];
+                load_row<T, RP>(tw + fft_tw_off(N, P) + 16 * k, w);
                 static_for<1, RP>([&](auto rc) {
                     constexpr int r = decltype(rc)::value;
-                    const cx<T> w = tab[(r * k * SC) & (2 * N - 1)];
-                    if constexpr (DIR > 0) v[u * RP + r] = cmul(v[u * RP + r], w);
-                    else v[u * RP + r] = cmul_conj(v[u * RP + r], w);
+                    if constexpr (DIR > 0) v[u * RP + r] = cmul(v[u * RP + r], w[r]);
+                    else v[u * RP + r] = cmul_conj(v[u * RP + r], w[r]);
                 });
             }
             dft<T, DIR, RP>(&v[u * RP]);
@@ -170,20 +204,27 @@ struct Fft {
             constexpr int u = decltype(uc)::value;
             const int jb = t + u * TPF;
             const int k = jb & (NS - 1);
-            const int base = (jb - k) * RP + k;
+            // base = (jb / NS) * NS * RP + k; element r sits at base + r * NS.
+            // NS == 1: base = 16 jb, pad(base + r) = 17 jb + r.
+            // NS >= 16: pad(base + r NS) = pad(base) + 17 r NS / 16.
+            const int pb = pad((jb - k) * RP + k);
             static_for<0, RP>([&](auto rc) {
                 constexpr int r = decltype(rc)::value;
-                const int idx = pad(base + r * NS);
+                const int idx = pb + r * NS + (r * NS) / 16;
                 lre[idx] = v[u * RP + r].re;
                 lim[idx] = v[u * RP + r].im;
             });
         });
         __syncthreads();
+        const int pt = pad(t);
         static_for<0, R / RQ>([&](auto uc) {
             constexpr int u = decltype(uc)::value;
             static_for<0, RQ>([&](auto rc) {
                 constexpr int r = decltype(rc)::value;
-                const int idx = pad(t + u * TPF + r * (N / RQ));
+                constexpr int C = u * TPF + r * (N / RQ);
+                int idx;
+                if constexpr (TPF % 16 == 0) idx = pad_add<C>(pt);
+                else idx = pad(t + C);
                 v[u * RQ + r] = cx<T>{lre[idx], lim[idx]};
             });
         });
@@ -192,10 +233,10 @@ struct Fft {
     // Full transform: X_m = sum_n x_n exp(DIR 2 pi i n m / N), unnormalised.
     template <int DIR>
     static __device__ __forceinline__ void run(cx<T> (&v)[R], int t, T *lre, T *lim,
-                                               const cx<T> *__restrict__ tab) {
+                                               const cx<T> *__restrict__ tw) {
         static_for<0, NPASS>([&](auto pc) {
             constexpr int p = decltype(pc)::value;
-            pass<DIR, p>(v, t, tab);
+            pass<DIR, p>(v, t, tw);
             if constexpr (p + 1 < NPASS) exchange<p>(v, t, lre, lim);
         });
     }

@@ -60,11 +60,58 @@ __device__ __forceinline__ float expm1_t<float>(float x) { return expm1f(x); }
 template <>
 __device__ __forceinline__ double expm1_t<double>(double x) { return expm1(x); }
 
+template <typename T>
+__device__ __forceinline__ T fma_t(T a, T b, T c) { return __builtin_fma(a, b, c); }
+template <>
+__device__ __forceinline__ float fma_t<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 // ----------------------------------------------------------------- sweep
+
+// delta-f source of one line along the thread's output positions
+// pos_k = (p0 + k TPF) mod N, k = 0..R-1 (Section 3.1):
+//   f_eq(v - tau E) - f_eq(v) = sum_g f_g(v) expm1(A_g v + C_g),
+//   A_g = tau E / sigma_g^2, C_g = -A_g c_g - (tau E)^2 / (2 sigma_g^2).
+// expm1 is evaluated exactly at k = 0 and where the positions wrap around
+// the periodic velocity grid; in between it follows the exact identity
+// expm1(y + d) = expm1(y) + expm1(d) (1 + expm1(y)), d = A_g TPF dv.
+template <typename T, int N, int R, int TPF>
+__device__ __forceinline__ void deltaf_source(const SimDev &S, double tauE, int p0,
+                                              T (&src)[R]) {
+    static_for<0, R>([&](auto kc) { src[decltype(kc)::value] = (T)0; });
+    const T *fg = (const T *)S.feq_g;
+    const T vmin = (T)S.vmin, dv = (T)S.dv;
+    for (int g = 0; g < S.n_feq; ++g) {
+        const double is2 = S.feq_inv_s2[g];
+        const double A64 = tauE * is2;
+        const T A = (T)A64;
+        const T C = (T)(-A64 * S.feq_c[g] - 0.5 * tauE * tauE * is2);
+        const T rm1 = expm1_t<T>((T)(A64 * (double)TPF * S.dv));
+        const T *row = fg + g * N;
+        T e = expm1_t<T>(A * (vmin + (T)p0 * dv) + C);
+        static_for<0, R>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            const int raw = p0 + k * TPF;
+            const int pos = raw & (N - 1);
+            if constexpr (k > 0) {
+                const bool wraps_here = raw >= N && raw - TPF < N;
+                if (wraps_here) e = expm1_t<T>(A * (vmin + (T)pos * dv) + C);
+                else e = e + fma_t<T>(rm1, e, rm1);
+            }
+            src[k] = fma_t<T>(row[pos], e, src[k]);
+        });
+    }
+}
 
 // KIND 0: v-advection by tau = b.a[sim] with field E (lines are x-columns of
 // f, length nv).  KIND 1: x-advection by dt = b.a[sim] (lines are v-rows of
 // the transposed copy g, length nx).
+//
+// Two real lines A, B are packed as z = uA + i uB and transformed together.
+// With beta = b + s (b integer, s in [0,1)), the circulant A of Section 1.2 is
+// the cyclic shift by b composed with the Lagrange kernel w_q(s), q = -d..d+1.
+// The kernel is applied in Fourier space through its symbol
+//   S_m = sum_q w_q exp(2 pi i m q / N),
+// and the shift by b is applied exactly on the store (index j -> j - b mod N).
 template <typename T, int N, int KIND>
 __global__ __launch_bounds__(256) void sweep_kernel(const Batch b) {
     using F = Fft<T, N>;
@@ -85,7 +132,8 @@ __global__ __launch_bounds__(256) void sweep_kernel(const Batch b) {
     const int lineB = lineA + 1;
     T *lre = lds[slot][0];
     T *lim = lds[slot][1];
-    const cx<T> *tab = (const cx<T> *)(KIND == 0 ? S.tab_v : S.tab_x);
+    const cx<T> *tw = (const cx<T> *)(KIND == 0 ? S.tw_v : S.tw_x);
+    const cx<T> *eps = (const cx<T> *)(KIND == 0 ? S.eps_v : S.eps_x) + t * kEpsRow;
     T *data = (T *)(KIND == 0 ? S.f : S.g);
     T *pA = data + (size_t)lineA * N;
     T *pB = data + (size_t)lineB * N;
@@ -127,139 +175,121 @@ __global__ __launch_bounds__(256) void sweep_kernel(const Batch b) {
         v[r] = active ? cx<T>{pA[j], pB[j]} : cx<T>{(T)0, (T)0};
     });
 
-    F::template run<-1>(v, t, lre, lim, tab);  // v[i] = Z[t + TPF kpos(i)]
-
-    // Partner values conj(Z[N - m]) needed to separate the two real lines.
-    cx<T> W[R];
-    if constexpr (TPF > 1) {
-        __syncthreads();
-        static_for<0, R>([&](auto ic) {
-            constexpr int i = decltype(ic)::value;
-            const int idx = F::pad(t + TPF * F::kpos(i));
-            lre[idx] = v[i].re;
-            lim[idx] = v[i].im;
-        });
-        __syncthreads();
-        static_for<0, R>([&](auto ic) {
-            constexpr int i = decltype(ic)::value;
-            const int m = t + TPF * F::kpos(i);
-            const int idx = F::pad((N - m) & (N - 1));
-            W[i] = cx<T>{lre[idx], -lim[idx]};
-        });
-    } else {
-        __syncthreads();  // weights visible
-        static_for<0, R>([&](auto ic) {
-            constexpr int i = decltype(ic)::value;
-            constexpr int mm = (N - F::kpos(i)) & (N - 1);
-            constexpr int ip = F::kinv(mm);
-            W[i] = cx<T>{v[ip].re, -v[ip].im};
-        });
-    }
+    F::template run<-1>(v, t, lre, lim, tw);  // v[i] = Z[t + TPF kpos(i)]
 
     // Symbol of the fractional-shift kernel for the modes m = t + k TPF:
     //   S_m = sum_q w_q exp(2 pi i m q / N) = DFT_R^+ (H)[k],
     //   H_c = sum_{q = c mod R} w_q exp(2 pi i t q / N).
     // The packed product is Y_m = P_m Z_m + Q_m conj(Z_{N-m}) with P, Q the
     // symbols of wP, wQ.
-    cx<T> Y[R];
-    {
-        cx<T> H[R];
+    auto symbol = [&](int which, cx<T>(&H)[R]) {
+        cx<T> e[kEpsRow];
+        load_row<T, kEpsRow>(eps, e);
         static_for<0, R>([&](auto cc) { H[decltype(cc)::value] = cx<T>{(T)0, (T)0}; });
         static_for<0, kTaps>([&](auto qc) {
             constexpr int qi = decltype(qc)::value;
             constexpr int q = qi - kDMax;
             constexpr int c = ((q % R) + R) % R;
-            const T w = wsh[slot][0][qi];
+            constexpr int aq = q < 0 ? -q : q;
+            const T w = wsh[slot][which][qi];
             if constexpr (q == 0) {
                 H[c].re += w;
+            } else if constexpr (q > 0) {
+                H[c].re = fma_t<T>(w, e[aq].re, H[c].re);
+                H[c].im = fma_t<T>(w, e[aq].im, H[c].im);
             } else {
-                const int aq = q < 0 ? -q : q;
-                cx<T> e = tab[(2 * t * aq) & (2 * N - 1)];
-                if constexpr (q < 0) e.im = -e.im;
-                H[c].re += w * e.re;
-                H[c].im += w * e.im;
+                H[c].re = fma_t<T>(w, e[aq].re, H[c].re);
+                H[c].im = fma_t<T>(-w, e[aq].im, H[c].im);
             }
         });
         dft<T, 1, R>(H);
+    };
+
+    cx<T> Y[R];
+    if constexpr (TPF > 1) {
+        // Z to LDS at its natural position for the partner exchange.
+        __syncthreads();
+        const int pt = F::pad(t);
+        static_for<0, R>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            constexpr int C = TPF * F::kpos(i);
+            const int idx = (TPF % 16 == 0) ? F::template pad_add<C>(pt) : F::pad(t + C);
+            lre[idx] = v[i].re;
+            lim[idx] = v[i].im;
+        });
+        {
+            cx<T> H[R];
+            symbol(0, H);
+            static_for<0, R>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                constexpr int k = F::kpos(i);
+                Y[k] = cmul(H[k], v[i]);
+            });
+        }
+        __syncthreads();
+        {
+            cx<T> H[R];
+            symbol(1, H);
+            // partner index of m = t + k TPF is N - m = tp + (R - 1 - k) TPF for
+            // t > 0 (tp = TPF - t) and (R - k) TPF mod N for t = 0.
+            const int ptp = F::pad(TPF - t);
+            static_for<0, R>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                constexpr int C1 = (R - 1 - k) * TPF;
+                constexpr int C0 = ((R - k) % R) * TPF;
+                const int idx = t == 0 ? F::pad(C0)
+                                       : ((TPF % 16 == 0) ? F::template pad_add<C1>(ptp)
+                                                          : F::pad(TPF - t + C1));
+                const cx<T> Wk = cx<T>{lre[idx], -lim[idx]};
+                Y[k] = Y[k] + cmul(H[k], Wk);
+            });
+        }
+    } else {
+        __syncthreads();  // weights visible
+        cx<T> H[R];
+        symbol(0, H);
         static_for<0, R>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
             constexpr int k = F::kpos(i);
             Y[k] = cmul(H[k], v[i]);
         });
-    }
-    {
-        cx<T> H[R];
-        static_for<0, R>([&](auto cc) { H[decltype(cc)::value] = cx<T>{(T)0, (T)0}; });
-        static_for<0, kTaps>([&](auto qc) {
-            constexpr int qi = decltype(qc)::value;
-            constexpr int q = qi - kDMax;
-            constexpr int c = ((q % R) + R) % R;
-            const T w = wsh[slot][1][qi];
-            if constexpr (q == 0) {
-                H[c].re += w;
-            } else {
-                const int aq = q < 0 ? -q : q;
-                cx<T> e = tab[(2 * t * aq) & (2 * N - 1)];
-                if constexpr (q < 0) e.im = -e.im;
-                H[c].re += w * e.re;
-                H[c].im += w * e.im;
-            }
-        });
-        dft<T, 1, R>(H);
+        symbol(1, H);
         static_for<0, R>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
             constexpr int k = F::kpos(i);
-            Y[k] = Y[k] + cmul(H[k], W[i]);
+            constexpr int ip = F::kinv((N - k) & (N - 1));
+            Y[k] = Y[k] + cmul(H[k], cx<T>{v[ip].re, -v[ip].im});
         });
     }
 
-    F::template run<1>(Y, t, lre, lim, tab);  // Y[i] = y[t + TPF kpos(i)]
+    F::template run<1>(Y, t, lre, lim, tw);  // Y[i] = y[t + TPF kpos(i)]
 
     if (!active) return;
 
     // Store: unshifted index j goes to line position (j - b) mod N.
-    const int bmA = (int)(bA & (N - 1));
-    const int bmB = (int)(bB & (N - 1));
+    const int p0A = (t - (int)(bA & (N - 1))) & (N - 1);
+    const int p0B = (t - (int)(bB & (N - 1))) & (N - 1);
     if constexpr (KIND == 0) {
         if (S.deltaf) {
-            // f_eq(v - tau E) - f_eq(v) = sum_g f_g(v) expm1(A_g (v - c_g) + B_g),
-            // A_g = tau E / sigma_g^2, B_g = -(tau E)^2 / (2 sigma_g^2).
-            T Ag[VOG_MAX_FEQ][2], Bg[VOG_MAX_FEQ][2], cg[VOG_MAX_FEQ];
-            const double dA = arg * EA, dB = arg * EB;
-            for (int g = 0; g < VOG_MAX_FEQ; ++g) {
-                const double is2 = g < S.n_feq ? S.feq_inv_s2[g] : 0.0;
-                Ag[g][0] = (T)(dA * is2);
-                Ag[g][1] = (T)(dB * is2);
-                Bg[g][0] = (T)(-0.5 * dA * dA * is2);
-                Bg[g][1] = (T)(-0.5 * dB * dB * is2);
-                cg[g] = (T)S.feq_c[g];
-            }
-            const T *fg = (const T *)S.feq_g;
-            const T vmin = (T)S.vmin, dv = (T)S.dv;
-            const int nfeq = S.n_feq;
-            static_for<0, R>([&](auto ic) {
-                constexpr int i = decltype(ic)::value;
-                const int j = t + TPF * F::kpos(i);
-                const int posA = (j - bmA) & (N - 1);
-                const int posB = (j - bmB) & (N - 1);
-                const T vA = vmin + (T)posA * dv;
-                const T vB = vmin + (T)posB * dv;
-                T srcA = (T)0, srcB = (T)0;
-                for (int g = 0; g < nfeq; ++g) {
-                    srcA += fg[g * N + posA] * expm1_t<T>(Ag[g][0] * (vA - cg[g]) + Bg[g][0]);
-                    srcB += fg[g * N + posB] * expm1_t<T>(Ag[g][1] * (vB - cg[g]) + Bg[g][1]);
-                }
-                pA[posA] = Y[i].re + srcA;
-                pB[posB] = Y[i].im + srcB;
+            T src[R];
+            deltaf_source<T, N, R, TPF>(S, arg * EA, p0A, src);
+            static_for<0, R>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                pA[(p0A + k * TPF) & (N - 1)] = Y[F::kinv(k)].re + src[k];
+            });
+            deltaf_source<T, N, R, TPF>(S, arg * EB, p0B, src);
+            static_for<0, R>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                pB[(p0B + k * TPF) & (N - 1)] = Y[F::kinv(k)].im + src[k];
             });
             return;
         }
     }
-    static_for<0, R>([&](auto ic) {
-        constexpr int i = decltype(ic)::value;
-        const int j = t + TPF * F::kpos(i);
-        pA[(j - bmA) & (N - 1)] = Y[i].re;
-        pB[(j - bmB) & (N - 1)] = Y[i].im;
+    static_for<0, R>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        constexpr int i = F::kinv(k);
+        pA[(p0A + k * TPF) & (N - 1)] = Y[i].re;
+        pB[(p0B + k * TPF) & (N - 1)] = Y[i].im;
     });
 }
 
@@ -287,8 +317,8 @@ LaunchFn sweep_launcher(bool fp64, int n, bool vsweep) {
 // ----------------------------------------------------------------- transpose
 
 // TO_V false: f [nx][nv] -> g [nv][nx].  TO_V true: g [nv][nx] -> f [nx][nv]
-// and part[jt][i] = sum of the tile's (up to 64) velocities of column i,
-// accumulated in FP64 in a fixed order.
+// and part[jt][i] = FP64 sum of the tile's (up to 64) velocities of column
+// i, accumulated in a fixed order.  One 64 x 64 tile per block.
 template <typename T, bool TO_V>
 __global__ __launch_bounds__(256) void transpose_kernel(const Batch b) {
     __shared__ T tile[kTile][kTile + 1];
@@ -303,11 +333,13 @@ __global__ __launch_bounds__(256) void transpose_kernel(const Batch b) {
     if (tr >= tilesR) return;
     const int r0 = tr * kTile, c0 = tc * kTile;
     const int tx = threadIdx.x & (kTile - 1), ty = threadIdx.x / kTile;
+#pragma unroll
     for (int rr = ty; rr < kTile; rr += 256 / kTile) {
         const int r = r0 + rr, c = c0 + tx;
         if (r < rows && c < cols) tile[rr][tx] = in[(size_t)r * cols + c];
     }
     __syncthreads();
+#pragma unroll
     for (int cc = ty; cc < kTile; cc += 256 / kTile) {
         const int c = c0 + cc, r = r0 + tx;
         if (r < rows && c < cols) out[(size_t)c * rows + r] = tile[tx][cc];
@@ -325,6 +357,29 @@ __global__ __launch_bounds__(256) void transpose_kernel(const Batch b) {
     }
 }
 
+// rho_i = dv sum_p part[p][i] + feq_const, partial rows summed in order.
+__global__ __launch_bounds__(256) void rho_reduce_kernel(const Batch b) {
+    __shared__ double red[4][kTile];
+    const SimDev &S = *b.s[blockIdx.y];
+    const int i = blockIdx.x * kTile + (threadIdx.x & (kTile - 1));
+    const int ty = threadIdx.x / kTile;
+    if ((int)blockIdx.x * kTile >= S.nx) return;
+    const int np = S.nparts;
+    double acc = 0.0;
+    if (i < S.nx)
+        for (int p = ty; p < np; p += 4) acc += S.part[(size_t)p * S.nx + i];
+    red[ty][threadIdx.x & (kTile - 1)] = acc;
+    __syncthreads();
+    if (ty == 0 && i < S.nx) {
+        const int tx = threadIdx.x;
+        S.rho[i] = S.dv * (((red[0][tx] + red[1][tx]) + red[2][tx]) + red[3][tx]) + S.feq_const;
+    }
+}
+
+void launch_rho_reduce(const Batch &b, int max_nx, hipStream_t st) {
+    hipLaunchKernelGGL(rho_reduce_kernel, dim3((max_nx + kTile - 1) / kTile, b.n), dim3(256), 0, st, b);
+}
+
 void launch_transpose(bool fp64, bool to_v, const Batch &b, int max_tiles, hipStream_t st) {
     dim3 grid(max_tiles, b.n), block(256);
     if (fp64) {
@@ -338,8 +393,7 @@ void launch_transpose(bool fp64, bool to_v, const Batch &b, int max_tiles, hipSt
 
 // ----------------------------------------------------------------- field solve
 
-// One block per sim, TPF = N/16 threads (N = nx).  rho_i = dv sum_p part[p][i]
-// + feq_const; rho_hat = FFT(rho); E_hat_m = rho_hat_m / (i k_m), with
+// One block per sim, TPF = N/16 threads (N = nx).  rho_hat = FFT(rho); E_hat_m = rho_hat_m / (i k_m), with
 // E_hat_0 = E_hat_{N/2} = 0 (Section 3.2, Fourier variant); E = iFFT / N.
 // Writes the step's diagnostics record.
 template <int N>
@@ -356,17 +410,13 @@ __global__ __launch_bounds__(kFieldThreads<N>) void field_kernel(const Batch b) 
 
     const SimDev &S = *b.s[blockIdx.x];
     const int t = threadIdx.x;
-    const cx<double> *tab = (const cx<double> *)S.tab_x64;
-    const int nparts = b.nparts[blockIdx.x];
+    const cx<double> *tab = (const cx<double> *)S.tw_x64;
     if (t == 0) bad[0] = 0;
 
     cx<double> v[R];
     static_for<0, R>([&](auto rc) {
         constexpr int r = decltype(rc)::value;
-        const int i = t + r * TPF;
-        double acc = 0.0;
-        for (int p = 0; p < nparts; ++p) acc += S.part[(size_t)p * N + i];
-        v[r] = cx<double>{acc * S.dv + S.feq_const, 0.0};
+        v[r] = cx<double>{S.rho[t + r * TPF], 0.0};
     });
     F::template run<-1>(v, t, lre, lim, tab);
 
@@ -447,8 +497,8 @@ LaunchFn field_launcher(int nx) {
 
 // ----------------------------------------------------------------- rho (v layout)
 
-// part[i] = sum_j f[i][j] in FP64 with a fixed reduction order (one block per
-// x-column); used when the field is computed from a freshly set f.
+// rho_i = dv sum_j f[i][j] + feq_const in FP64 with a fixed reduction order
+// (one block per x-column); used when the field is computed from a freshly set f.
 template <typename T>
 __global__ __launch_bounds__(256) void rho_v_kernel(const Batch b) {
     __shared__ double red[256];
@@ -464,7 +514,7 @@ __global__ __launch_bounds__(256) void rho_v_kernel(const Batch b) {
         if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
         __syncthreads();
     }
-    if (threadIdx.x == 0) S.part[i] = red[0];
+    if (threadIdx.x == 0) S.rho[i] = S.dv * red[0] + S.feq_const;
 }
 
 void launch_rho_v(bool fp64, const Batch &b, int max_nx, hipStream_t st) {

@@ -12,6 +12,7 @@
 #include <string>
 #include <vector>
 
+#include "fft.hpp"
 #include "vog_internal.hpp"
 
 using namespace vog;
@@ -70,7 +71,7 @@ void unit_roots(int n, std::vector<double> &re, std::vector<double> &im) {
 }
 
 struct Layout {
-    size_t f, g, E, part, mom, tab_x, tab_v, tab_x64, feq_g, feq64, ring, dev, total;
+    size_t f, g, E, part, rho, mom, tw_x, tw_v, eps_x, eps_v, tw_x64, feq_g, feq64, ring, dev, total;
 };
 
 Layout layout_of(const vog_config &c) {
@@ -88,10 +89,13 @@ Layout layout_of(const vog_config &c) {
     L.g = take(cells * es);
     L.E = take(sizeof(double) * c.nx);
     L.part = take(sizeof(double) * c.nx * (size_t)nparts);
+    L.rho = take(sizeof(double) * c.nx);
     L.mom = take(sizeof(double) * 2 * c.nx);
-    L.tab_x = take(2 * es * 2 * c.nx);
-    L.tab_v = take(2 * es * 2 * c.nv);
-    L.tab_x64 = take(2 * sizeof(double) * 2 * c.nx);
+    L.tw_x = take(2 * es * fft_tw_total(c.nx));
+    L.tw_v = take(2 * es * fft_tw_total(c.nv));
+    L.eps_x = take(2 * es * kEpsRow * (c.nx / fft_regs(c.nx)));
+    L.eps_v = take(2 * es * kEpsRow * (c.nv / fft_regs(c.nv)));
+    L.tw_x64 = take(2 * sizeof(double) * fft_tw_total(c.nx));
     L.feq_g = take(es * VOG_MAX_FEQ * c.nv);
     L.feq64 = take(sizeof(double) * c.nv);
     L.ring = take(sizeof(vog_diag) * kRingCap);
@@ -168,21 +172,52 @@ double feq_at(const vog_config &c, double v) {
     return acc;
 }
 
+int upload(void *dst, const void *src, size_t bytes, hipStream_t st) {
+    HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
+    return VOG_OK;
+}
+
+// Twiddle rows of the FFT passes p >= 1 (layout of fft.hpp): row k of pass p
+// holds exp(+2 pi i r k / (NS RP)), r < 16 (entries r >= RP are 1).
 template <typename T>
-std::vector<T> interleave_roots(int n) {
+std::vector<T> twiddle_rows(int n) {
     std::vector<double> re, im;
     unit_roots(n, re, im);
-    std::vector<T> out(4 * (size_t)n);
-    for (int k = 0; k < 2 * n; ++k) {
-        out[2 * k] = (T)re[k];
-        out[2 * k + 1] = (T)im[k];
+    std::vector<T> out(2 * (size_t)fft_tw_total(n), (T)0);
+    for (size_t k = 0; k < out.size(); k += 2) out[k] = (T)1;
+    for (int p = 1; p < fft_npass(n); ++p) {
+        const int NS = fft_ns(p), RP = fft_radix(n, p);
+        const int scale = 2 * (n / (NS * RP));
+        for (int k = 0; k < NS; ++k)
+            for (int r = 0; r < RP; ++r) {
+                const int idx = (r * k * scale) % (2 * n);
+                const size_t at = 2 * ((size_t)fft_tw_off(n, p) + 16 * (size_t)k + r);
+                out[at] = (T)re[idx];
+                out[at + 1] = (T)im[idx];
+            }
     }
     return out;
 }
 
-int upload(void *dst, const void *src, size_t bytes, hipStream_t st) {
-    HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
-    return VOG_OK;
+// Symbol table: row t < n / 16 holds exp(2 pi i t q / n), q < 10.
+template <typename T>
+std::vector<T> eps_rows(int n) {
+    std::vector<double> re, im;
+    unit_roots(n, re, im);
+    const int rows = n / fft_regs(n);
+    std::vector<T> out(2 * (size_t)rows * kEpsRow);
+    for (int t = 0; t < rows; ++t)
+        for (int q = 0; q < kEpsRow; ++q) {
+            const int idx = (int)((2LL * t * q) % (2 * n));
+            out[2 * ((size_t)t * kEpsRow + q)] = (T)re[idx];
+            out[2 * ((size_t)t * kEpsRow + q) + 1] = (T)im[idx];
+        }
+    return out;
+}
+
+template <typename T>
+int upload_vec(char *dst, const std::vector<T> &v, hipStream_t st) {
+    return upload(dst, v.data(), v.size() * sizeof(T), st);
 }
 
 // Profiling helpers: events around one grouped launch of a kind.
@@ -301,9 +336,24 @@ int run_transpose(vog_sim *lead, const std::vector<vog_sim *> &sims, bool to_v) 
     return VOG_OK;
 }
 
-// Field solve for all sims; nparts = number of partial rows in part.
+// rho from the partial sums of the x->v transpose.
+int run_rho_reduce(vog_sim *lead, const std::vector<vog_sim *> &sims) {
+    Group g;
+    g.sims = sims;
+    return for_chunks(g, [&](const Batch &b, size_t base) {
+        int maxnx = 0;
+        for (int k = 0; k < b.n; ++k) maxnx = std::max(maxnx, g.sims[base + k]->cfg.nx);
+        EventPair *p;
+        prof_begin(lead, K_RHO, &p);
+        launch_rho_reduce(b, maxnx, lead->stream);
+        prof_end(lead, p);
+        return check_launch();
+    });
+}
+
+// Field solve (Poisson, E, diagnostics record) for all sims.
 int run_field(vog_sim *lead, const std::vector<vog_sim *> &sims, const std::vector<int64_t> &stepno,
-              const std::vector<double> &tnow, bool from_transpose) {
+              const std::vector<double> &tnow) {
     std::map<int, std::vector<size_t>> groups;  // nx -> indices
     for (size_t k = 0; k < sims.size(); ++k) groups[sims[k]->cfg.nx].push_back(k);
     for (auto &kv : groups) {
@@ -318,7 +368,6 @@ int run_field(vog_sim *lead, const std::vector<vog_sim *> &sims, const std::vect
                 b.s[k] = sims[i]->dev;
                 b.step[k] = stepno[i];
                 b.t[k] = tnow[i];
-                b.nparts[k] = from_transpose ? sims[i]->host_dev.nparts : 1;
             }
             EventPair *p;
             prof_begin(lead, K_FIELD, &p);
@@ -380,7 +429,7 @@ int field_from_f(vog_sim *s) {
     if (rc != VOG_OK) return rc;
     std::vector<int64_t> st{s->step};
     std::vector<double> tt{s->t};
-    return run_field(s, one, st, tt, false);
+    return run_field(s, one, st, tt);
 }
 
 int device_guard(vog_sim *s) {
@@ -406,7 +455,8 @@ int step_sims(const std::vector<vog_sim *> &sims, const std::vector<double> &dt,
         if ((rc = run_transpose(lead, sims, false)) != VOG_OK) return rc;
         if ((rc = run_sweep(lead, sims, dt, false)) != VOG_OK) return rc;
         if ((rc = run_transpose(lead, sims, true)) != VOG_OK) return rc;
-        if ((rc = run_field(lead, sims, stepno, tnow, true)) != VOG_OK) return rc;
+        if ((rc = run_rho_reduce(lead, sims)) != VOG_OK) return rc;
+        if ((rc = run_field(lead, sims, stepno, tnow)) != VOG_OK) return rc;
         if ((rc = run_sweep(lead, sims, tau, true)) != VOG_OK) return rc;
         std::vector<vog_sim *> msims;
         std::vector<int64_t> mstep;
@@ -508,10 +558,13 @@ int vog_create(const vog_config *c, void *dev_workspace, size_t bytes, void *hip
     D.g = s->ws + L.g;
     D.E = (double *)(s->ws + L.E);
     D.part = (double *)(s->ws + L.part);
+    D.rho = (double *)(s->ws + L.rho);
     D.mom = (double *)(s->ws + L.mom);
-    D.tab_x = s->ws + L.tab_x;
-    D.tab_v = s->ws + L.tab_v;
-    D.tab_x64 = (const double *)(s->ws + L.tab_x64);
+    D.tw_x = s->ws + L.tw_x;
+    D.tw_v = s->ws + L.tw_v;
+    D.eps_x = s->ws + L.eps_x;
+    D.eps_v = s->ws + L.eps_v;
+    D.tw_x64 = (const double *)(s->ws + L.tw_x64);
     D.feq_g = s->ws + L.feq_g;
     D.feq64 = (const double *)(s->ws + L.feq64);
     D.ring = (vog_diag *)(s->ws + L.ring);
@@ -543,7 +596,6 @@ int vog_create(const vog_config *c, void *dev_workspace, size_t bytes, void *hip
     s->dev = (const SimDev *)(s->ws + L.dev);
 
     // Host tables (FP64, rounded to the storage precision).
-    std::vector<double> tx64 = interleave_roots<double>(nx);
     std::vector<double> fg64((size_t)VOG_MAX_FEQ * nv, 0.0);
     for (int g = 0; g < c->n_feq; ++g)
         for (int j = 0; j < nv; ++j) {
@@ -557,28 +609,35 @@ int vog_create(const vog_config *c, void *dev_workspace, size_t bytes, void *hip
     };
     launch_fill(s->ws, L.total, s->stream);
     if ((rc = check_launch()) != VOG_OK) return bail(rc);
-    std::vector<char> keep;  // host staging kept alive until the final sync
+    // Staging vectors stay alive until the synchronisation below.
+    const std::vector<double> tw64x = twiddle_rows<double>(nx);
+    const std::vector<double> tw64v = twiddle_rows<double>(nv);
+    const std::vector<double> ep64x = eps_rows<double>(nx);
+    const std::vector<double> ep64v = eps_rows<double>(nv);
+    std::vector<float> tw32x, tw32v, ep32x, ep32v, fg32;
     if (fp64) {
-        std::vector<double> tv = interleave_roots<double>(nv);
-        if ((rc = upload(s->ws + L.tab_x, tx64.data(), tx64.size() * 8, s->stream)) != VOG_OK) return bail(rc);
-        if ((rc = upload(s->ws + L.tab_v, tv.data(), tv.size() * 8, s->stream)) != VOG_OK) return bail(rc);
-        if ((rc = upload(s->ws + L.feq_g, fg64.data(), fg64.size() * 8, s->stream)) != VOG_OK) return bail(rc);
-        if ((rc = upload(s->ws + L.tab_x64, tx64.data(), tx64.size() * 8, s->stream)) != VOG_OK) return bail(rc);
-        if ((rc = upload(s->ws + L.feq64, s->feq64.data(), nv * 8, s->stream)) != VOG_OK) return bail(rc);
-        if ((rc = upload(s->ws + L.dev, &D, sizeof(D), s->stream)) != VOG_OK) return bail(rc);
-        if (hipStreamSynchronize(s->stream) != hipSuccess) return bail(fail(VOG_EDEVICE, "sync failed"));
+        if ((rc = upload_vec(s->ws + L.tw_x, tw64x, s->stream)) != VOG_OK) return bail(rc);
+        if ((rc = upload_vec(s->ws + L.tw_v, tw64v, s->stream)) != VOG_OK) return bail(rc);
+        if ((rc = upload_vec(s->ws + L.eps_x, ep64x, s->stream)) != VOG_OK) return bail(rc);
+        if ((rc = upload_vec(s->ws + L.eps_v, ep64v, s->stream)) != VOG_OK) return bail(rc);
+        if ((rc = upload_vec(s->ws + L.feq_g, fg64, s->stream)) != VOG_OK) return bail(rc);
     } else {
-        std::vector<float> tx = interleave_roots<float>(nx);
-        std::vector<float> tv = interleave_roots<float>(nv);
-        std::vector<float> fg(fg64.begin(), fg64.end());
-        if ((rc = upload(s->ws + L.tab_x, tx.data(), tx.size() * 4, s->stream)) != VOG_OK) return bail(rc);
-        if ((rc = upload(s->ws + L.tab_v, tv.data(), tv.size() * 4, s->stream)) != VOG_OK) return bail(rc);
-        if ((rc = upload(s->ws + L.feq_g, fg.data(), fg.size() * 4, s->stream)) != VOG_OK) return bail(rc);
-        if ((rc = upload(s->ws + L.tab_x64, tx64.data(), tx64.size() * 8, s->stream)) != VOG_OK) return bail(rc);
-        if ((rc = upload(s->ws + L.feq64, s->feq64.data(), nv * 8, s->stream)) != VOG_OK) return bail(rc);
-        if ((rc = upload(s->ws + L.dev, &D, sizeof(D), s->stream)) != VOG_OK) return bail(rc);
-        if (hipStreamSynchronize(s->stream) != hipSuccess) return bail(fail(VOG_EDEVICE, "sync failed"));
+        tw32x = twiddle_rows<float>(nx);
+        tw32v = twiddle_rows<float>(nv);
+        ep32x = eps_rows<float>(nx);
+        ep32v = eps_rows<float>(nv);
+        fg32.assign(fg64.begin(), fg64.end());
+        if ((rc = upload_vec(s->ws + L.tw_x, tw32x, s->stream)) != VOG_OK) return bail(rc);
+        if ((rc = upload_vec(s->ws + L.tw_v, tw32v, s->stream)) != VOG_OK) return bail(rc);
+        if ((rc = upload_vec(s->ws + L.eps_x, ep32x, s->stream)) != VOG_OK) return bail(rc);
+        if ((rc = upload_vec(s->ws + L.eps_v, ep32v, s->stream)) != VOG_OK) return bail(rc);
+        if ((rc = upload_vec(s->ws + L.feq_g, fg32, s->stream)) != VOG_OK) return bail(rc);
     }
+    if ((rc = upload_vec(s->ws + L.tw_x64, tw64x, s->stream)) != VOG_OK) return bail(rc);
+    if ((rc = upload_vec(s->ws + L.feq64, s->feq64, s->stream)) != VOG_OK) return bail(rc);
+    if ((rc = upload(s->ws + L.dev, &D, sizeof(D), s->stream)) != VOG_OK) return bail(rc);
+    // The staging vectors above are temporaries: wait until the copies are done.
+    if (hipStreamSynchronize(s->stream) != hipSuccess) return bail(fail(VOG_EDEVICE, "sync failed"));
     *out = s;
     return VOG_OK;
 }

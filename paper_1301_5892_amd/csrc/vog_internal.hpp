@@ -20,11 +20,14 @@ struct SimDev {
     void *f;            // [nx][nv]  f or delta f, storage precision (v fastest)
     void *g;            // [nv][nx]  transposed copy used by the x-sweep
     double *E;          // [nx]      field at the current time level
-    double *part;       // [nparts][nx] partial velocity sums for rho
+    double *part;       // [nparts][nx] partial velocity sums, one row per 64 velocities
+    double *rho;        // [nx]      charge density rho_i = int f dv
     double *mom;        // [nx][2]   per-line moment sums
-    const void *tab_x;  // [2 nx]    exp(i pi k / nx), storage precision (re, im)
-    const void *tab_v;  // [2 nv]    exp(i pi k / nv)
-    const double *tab_x64;  // [2 nx] FP64 copy for the field solve
+    const void *tw_x;   // FFT twiddle rows for length nx, storage precision (re, im)
+    const void *tw_v;   // FFT twiddle rows for length nv
+    const void *eps_x;  // [nx / 16][10] exp(2 pi i t q / nx), symbol table for the x-sweep
+    const void *eps_v;  // [nv / 16][10] exp(2 pi i t q / nv)
+    const double *tw_x64;  // FP64 twiddle rows for length nx (field solve)
     const void *feq_g;  // [n_feq][nv] component values f_g(v_j), storage precision
     const double *feq64;    // [nv] f_eq(v_j), FP64
     vog_diag *ring;     // [kRingCap]
@@ -43,10 +46,9 @@ struct Batch {
     double a[kMaxBatch];      // tau (v-sweep), dt (x-sweep)
     double t[kMaxBatch];      // time after the step (field solve)
     int64_t step[kMaxBatch];  // step number after the step (field solve)
-    int nparts[kMaxBatch];    // number of rho partial rows to sum (field solve)
 };
 
-enum Kind { K_SWEEP_V = 0, K_SWEEP_X = 1, K_T_VX = 2, K_T_XV = 3, K_FIELD = 4, K_MOMENTS = 5 };
+enum Kind { K_SWEEP_V = 0, K_SWEEP_X = 1, K_T_VX = 2, K_T_XV = 3, K_FIELD = 4, K_MOMENTS = 5, K_RHO = 6 };
 
 // Host-side launchers (defined in kernels.hip).
 using LaunchFn = void (*)(const Batch &, int max_lines, hipStream_t);
@@ -54,6 +56,7 @@ LaunchFn sweep_launcher(bool fp64, int n, bool vsweep);
 void launch_transpose(bool fp64, bool to_v, const Batch &b, int max_tiles, hipStream_t st);
 LaunchFn field_launcher(int nx);
 void launch_rho_v(bool fp64, const Batch &b, int max_nx, hipStream_t st);
+void launch_rho_reduce(const Batch &b, int max_nx, hipStream_t st);
 void launch_moments(bool fp64, const Batch &b, int max_nx, hipStream_t st);
 void launch_init(bool fp64, const SimDev *s, int cells, int nmodes, const double *amp,
                  const double *kx, const double *ph, hipStream_t st);

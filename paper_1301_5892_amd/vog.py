@@ -21,8 +21,9 @@ FP64_PLAIN, FP32_DELTAF, FP64_DELTAF = 0, 1, 2
 POISSON_FOURIER = 0
 FIELD_SELF_CONSISTENT, FIELD_ZERO = 0, 1
 MAX_FEQ = 4
-NUM_KINDS = 6
-KIND_NAMES = ("sweep_v", "sweep_x", "transpose_vx", "transpose_xv_rho", "field", "moments")
+NUM_KINDS = 7
+KIND_NAMES = ("sweep_v", "sweep_x", "transpose_vx", "transpose_xv_rho", "field", "moments",
+              "rho_reduce")
 PRECISION = {"fp64_plain": FP64_PLAIN, "fp32_deltaf": FP32_DELTAF, "fp64_deltaf": FP64_DELTAF}
 
 
