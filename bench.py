@@ -4,8 +4,9 @@ Default workload: the 4096 x 4096 large-grid case (FP32 delta f, degree 17,
 dt = 0.02), the configuration the metric is quoted on.  One "step" is one
 full Strang step (v-sweep, transpose, x-sweep, transpose + rho, field solve,
 v-sweep).  The timed region holds exactly --steps steps, bracketed by device
-synchronisation; HIP events recorded on the sims's stream around every
-kernel launch inside the timed region give each kernel's average duration.
+synchronisation.  A second pass of the same number of steps records HIP events
+on the sim's stream around every kernel launch; they give each kernel's
+average duration for the roofline.
 
 Prints one JSON line with the headline FP32 delta-f rate, the FP64 plain
 rate on the same GPU, the roofline of the dominant kernel, the CPU-oracle
@@ -40,6 +41,9 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--no-serving", action="store_true")
     p.add_argument("--serving-requests", type=int, default=512)
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="run one plain 256 MiB device-to-device copy first (a known-size "
+                        "kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
     return p.parse_args()
 
 
@@ -67,25 +71,34 @@ def stored_traffic(kind: str, workload: str, precision: str):
 
 
 def run_gpu(w, precision, steps, warmup):
+    """Times `steps` Strang steps twice on one sim: first plain (the headline
+    rate), then with HIP events recorded around every launch (per-kernel
+    average durations for the roofline)."""
     import torch
     from paper_1301_5892_amd import vog
 
     sim = vog.Sim(w, precision=precision).init()
     sim.step(warmup)
     sim.sync()
-    sim.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.step(steps)
     sim.sync()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    sim.profile(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sim.step(steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    elapsed_prof = time.perf_counter() - t1
     prof = sim.profile_read()
     sim.profile(False)
     d = sim.diag()
     finite = bool(d.size == 0 or d["finite"][-1] == 1)
     sim.close()
-    return elapsed, prof, finite
+    return elapsed, prof, finite, elapsed_prof
 
 
 def roofline_for(w, precision, prof, steps):
@@ -151,8 +164,14 @@ def main():
     vog.load()
     w = getattr(workloads, args.workload)()
     K, W = args.steps, args.warmup
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
-    el32, prof32, fin32 = run_gpu(w, "fp32_deltaf", K, W)
+    el32, prof32, fin32, el32p = run_gpu(w, "fp32_deltaf", K, W)
     value = w.cells * K / el32
     out = {
         "metric": "phase-space cell-updates/s per split step, FP32-δf vs FP64; p99 req latency",
@@ -170,6 +189,7 @@ def main():
         "config": {"workload": w.name, "nx": w.nx, "nv": w.nv, "precision": "fp32_deltaf",
                    "degree": w.degree, "dt": w.dt, "L": w.L, "vmin": w.vmin, "vmax": w.vmax},
         "finite": fin32,
+        "ms_per_step_with_kernel_events": el32p / K * 1e3,
         "kernels_ms_per_step": {k: v[0] / K for k, v in prof32.items()},
         "roofline": roofline_for(w, "fp32_deltaf", prof32, K),
         "paper_context": {"value": 2.047e8, "unit": "cell-updates/s",
@@ -178,8 +198,9 @@ def main():
         "build": vog.build_info(),
     }
     if not args.no_fp64:
-        el64, prof64, fin64 = run_gpu(w, "fp64_plain", K, W)
+        el64, prof64, fin64, el64p = run_gpu(w, "fp64_plain", K, W)
         out["fp64_plain"] = {"value": w.cells * K / el64, "ms_per_step": el64 / K * 1e3,
+                             "ms_per_step_with_kernel_events": el64p / K * 1e3,
                              "finite": fin64,
                              "kernels_ms_per_step": {k: v[0] / K for k, v in prof64.items()},
                              "roofline": roofline_for(w, "fp64_plain", prof64, K)}

@@ -98,9 +98,10 @@ void vog_config_default(vog_config *cfg);
 /* Checks every field of *cfg; VOG_OK or VOG_EINVAL. */
 int vog_config_validate(const vog_config *cfg);
 
-/* Exact number of device bytes a sim of this configuration uses (f, its
- * transposed scratch copy, field, partial sums, tables, diagnostics ring).
- * Returns 0 for an invalid configuration. */
+/* Exact number of device bytes a sim of this configuration uses (f, a
+ * transposed scratch copy when the x-sweep cannot run on the v-fastest
+ * layout (nx < 256 or nv smaller than one tile of x-lines), field, partial
+ * sums, tables, diagnostics ring).  Returns 0 for an invalid configuration. */
 size_t vog_workspace_bytes(const vog_config *cfg);
 
 /* Creates a sim on the current HIP device.  dev_workspace: device memory of

@@ -131,6 +131,14 @@ __device__ __forceinline__ void dft(cx<T> *v) {
     }
 }
 
+// Returns p unchanged but opaque to the optimiser: loads through the result
+// cannot be merged with, or hoisted above, loads through p.
+template <typename P>
+__device__ __forceinline__ P opaque(P p) {
+    asm volatile("" : "+v"(p));
+    return p;
+}
+
 // Loads entries [0, n) of a table row (n even, row 16-byte aligned).
 template <typename T, int NE>
 __device__ __forceinline__ void load_row(const cx<T> *__restrict__ row, cx<T> (&out)[NE]) {

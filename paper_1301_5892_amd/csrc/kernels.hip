@@ -71,15 +71,18 @@ __device__ __forceinline__ float fma_t<float>(float a, float b, float c) { retur
 // pos_k = (p0 + k TPF) mod N, k = 0..R-1 (Section 3.1):
 //   f_eq(v - tau E) - f_eq(v) = sum_g f_g(v) expm1(A_g v + C_g),
 //   A_g = tau E / sigma_g^2, C_g = -A_g c_g - (tau E)^2 / (2 sigma_g^2).
-// expm1 is evaluated exactly at k = 0 and where the positions wrap around
-// the periodic velocity grid; in between it follows the exact identity
-// expm1(y + d) = expm1(y) + expm1(d) (1 + expm1(y)), d = A_g TPF dv.
+// The positions increase by TPF and wrap around the periodic velocity grid
+// at most once, at k = kw.  expm1 is evaluated exactly at k = 0 and at k = kw;
+// in between it follows the exact identity
+//   expm1(y + d) = expm1(y) + expm1(d) (1 + expm1(y)),  d = A_g TPF dv.
 template <typename T, int N, int R, int TPF>
 __device__ __forceinline__ void deltaf_source(const SimDev &S, double tauE, int p0,
                                               T (&src)[R]) {
     static_for<0, R>([&](auto kc) { src[decltype(kc)::value] = (T)0; });
     const T *fg = (const T *)S.feq_g;
     const T vmin = (T)S.vmin, dv = (T)S.dv;
+    const int kw = (N - p0 + TPF - 1) / TPF;  // first wrapped k (R when none)
+    const int pw = p0 + kw * TPF - N;         // its position
     for (int g = 0; g < S.n_feq; ++g) {
         const double is2 = S.feq_inv_s2[g];
         const double A64 = tauE * is2;
@@ -87,19 +90,138 @@ __device__ __forceinline__ void deltaf_source(const SimDev &S, double tauE, int 
         const T C = (T)(-A64 * S.feq_c[g] - 0.5 * tauE * tauE * is2);
         const T rm1 = expm1_t<T>((T)(A64 * (double)TPF * S.dv));
         const T *row = fg + g * N;
-        T e = expm1_t<T>(A * (vmin + (T)p0 * dv) + C);
+        const T e0 = expm1_t<T>(fma_t<T>(A, vmin + (T)p0 * dv, C));
+        const T ew = expm1_t<T>(fma_t<T>(A, vmin + (T)(kw < R ? pw : 0) * dv, C));
+        T e = e0;
         static_for<0, R>([&](auto kc) {
             constexpr int k = decltype(kc)::value;
-            const int raw = p0 + k * TPF;
-            const int pos = raw & (N - 1);
             if constexpr (k > 0) {
-                const bool wraps_here = raw >= N && raw - TPF < N;
-                if (wraps_here) e = expm1_t<T>(A * (vmin + (T)pos * dv) + C);
-                else e = e + fma_t<T>(rm1, e, rm1);
+                const T er = e + fma_t<T>(rm1, e, rm1);
+                e = k == kw ? ew : er;
             }
-            src[k] = fma_t<T>(row[pos], e, src[k]);
+            src[k] = fma_t<T>(row[(p0 + k * TPF) & (N - 1)], e, src[k]);
         });
     }
+}
+
+// Weights of a line pair for its fractional shifts sA, sB, combined for the
+// packed transform: wP = (wA + wB) / (2N), wQ = (wA - wB) / (2N) (the 1/N
+// folds the scale of the inverse FFT).  Threads t = 0.. of the pair share the
+// 2 x kTaps values; visible to the pair after the next barrier.
+template <typename T, int N, int TPF>
+__device__ __forceinline__ void pair_weights(int d, double sA, double sB, int t, T *wP, T *wQ) {
+    for (int qi = t; qi < kTaps; qi += TPF) {
+        const int q = qi - kDMax;
+        const double wa = lagrange_weight(d, q, sA);
+        const double wb = lagrange_weight(d, q, sB);
+        const double sc = 0.5 / (double)N;
+        wP[qi] = (T)((wa + wb) * sc);
+        wQ[qi] = (T)((wa - wb) * sc);
+    }
+}
+
+// The packed product of one line pair: on entry v[r] = z[t + r TPF] with
+// z = uA + i uB; on exit Y[i] = y[t + TPF kpos(i)], y = IFFT(P Z + Q conj(Z_{N-m}))
+// = (kernel A applied to uA) + i (kernel B applied to uB), unshifted.
+// The symbol of the fractional-shift kernel for the modes m = t + k TPF is
+//   S_m = sum_q w_q exp(2 pi i m q / N) = DFT_R^+ (H)[k],
+//   H_c = sum_{q = c mod R} w_q exp(2 pi i t q / N),
+// evaluated for the combined weights wP and wQ.  All threads of the block
+// must call this (it contains block barriers).
+template <typename T, int N, bool RELOAD_TW, int R = fft_regs(N)>
+__device__ __forceinline__ void pair_transform(cx<T> (&v)[R], cx<T> (&Y)[R], int t, T *lre, T *lim,
+                                               const cx<T> *__restrict__ tw,
+                                               const cx<T> *eps,
+                                               const T *wP, const T *wQ) {
+    using F = Fft<T, N>;
+    constexpr int TPF = F::TPF;
+    static_assert(R == F::R, "register count");
+
+    F::template run<-1>(v, t, lre, lim, tw);  // v[i] = Z[t + TPF kpos(i)]
+
+    auto symbol = [&](const T *w, cx<T>(&H)[R]) {
+        cx<T> e[kEpsRow];
+        load_row<T, kEpsRow>(eps, e);
+        static_for<0, R>([&](auto cc) { H[decltype(cc)::value] = cx<T>{(T)0, (T)0}; });
+        static_for<0, kTaps>([&](auto qc) {
+            constexpr int qi = decltype(qc)::value;
+            constexpr int q = qi - kDMax;
+            constexpr int c = ((q % R) + R) % R;
+            constexpr int aq = q < 0 ? -q : q;
+            const T wq = w[qi];
+            if constexpr (q == 0) {
+                H[c].re += wq;
+            } else if constexpr (q > 0) {
+                H[c].re = fma_t<T>(wq, e[aq].re, H[c].re);
+                H[c].im = fma_t<T>(wq, e[aq].im, H[c].im);
+            } else {
+                H[c].re = fma_t<T>(wq, e[aq].re, H[c].re);
+                H[c].im = fma_t<T>(-wq, e[aq].im, H[c].im);
+            }
+        });
+        dft<T, 1, R>(H);
+    };
+
+    if constexpr (TPF > 1) {
+        // Z to LDS at its natural position for the partner exchange.
+        __syncthreads();
+        const int pt = F::pad(t);
+        static_for<0, R>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            constexpr int C = TPF * F::kpos(i);
+            const int idx = (TPF % 16 == 0) ? F::template pad_add<C>(pt) : F::pad(t + C);
+            lre[idx] = v[i].re;
+            lim[idx] = v[i].im;
+        });
+        {
+            cx<T> H[R];
+            symbol(wP, H);
+            static_for<0, R>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                constexpr int k = F::kpos(i);
+                Y[k] = cmul(H[k], v[i]);
+            });
+        }
+        __syncthreads();
+        {
+            cx<T> H[R];
+            symbol(wQ, H);
+            // partner index of m = t + k TPF is N - m = tp + (R - 1 - k) TPF for
+            // t > 0 (tp = TPF - t) and (R - k) TPF mod N for t = 0.
+            const int ptp = F::pad(TPF - t);
+            static_for<0, R>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                constexpr int C1 = (R - 1 - k) * TPF;
+                constexpr int C0 = ((R - k) % R) * TPF;
+                const int idx = t == 0 ? F::pad(C0)
+                                       : ((TPF % 16 == 0) ? F::template pad_add<C1>(ptp)
+                                                          : F::pad(TPF - t + C1));
+                const cx<T> Wk = cx<T>{lre[idx], -lim[idx]};
+                Y[k] = Y[k] + cmul(H[k], Wk);
+            });
+        }
+    } else {
+        __syncthreads();  // weights visible
+        cx<T> H[R];
+        symbol(wP, H);
+        static_for<0, R>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            constexpr int k = F::kpos(i);
+            Y[k] = cmul(H[k], v[i]);
+        });
+        symbol(wQ, H);
+        static_for<0, R>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            constexpr int k = F::kpos(i);
+            constexpr int ip = F::kinv((N - k) & (N - 1));
+            Y[k] = Y[k] + cmul(H[k], cx<T>{v[ip].re, -v[ip].im});
+        });
+    }
+
+    // RELOAD_TW: re-read the twiddle rows instead of keeping the forward
+    // pass's rows live in registers (for kernels with a tight register budget).
+    if constexpr (RELOAD_TW) F::template run<1>(Y, t, lre, lim, opaque(tw));
+    else F::template run<1>(Y, t, lre, lim, tw);  // Y[i] = y[t + TPF kpos(i)]
 }
 
 // KIND 0: v-advection by tau = b.a[sim] with field E (lines are x-columns of
@@ -109,9 +231,8 @@ __device__ __forceinline__ void deltaf_source(const SimDev &S, double tauE, int 
 // Two real lines A, B are packed as z = uA + i uB and transformed together.
 // With beta = b + s (b integer, s in [0,1)), the circulant A of Section 1.2 is
 // the cyclic shift by b composed with the Lagrange kernel w_q(s), q = -d..d+1.
-// The kernel is applied in Fourier space through its symbol
-//   S_m = sum_q w_q exp(2 pi i m q / N),
-// and the shift by b is applied exactly on the store (index j -> j - b mod N).
+// The kernel is applied in Fourier space through its symbol and the shift by
+// b is applied exactly on the store (index j -> j - b mod N).
 template <typename T, int N, int KIND>
 __global__ __launch_bounds__(256) void sweep_kernel(const Batch b) {
     using F = Fft<T, N>;
@@ -123,10 +244,11 @@ __global__ __launch_bounds__(256) void sweep_kernel(const Batch b) {
     const int nlines = KIND == 0 ? S.nx : S.nv;
     const int npairs = nlines >> 1;
     if ((int)blockIdx.x * PPB >= npairs) return;  // whole block idle
+    const int blk = (int)blockIdx.x;
 
     const int slot = threadIdx.x / TPF;
     const int t = threadIdx.x % TPF;
-    const int pair = blockIdx.x * PPB + slot;
+    const int pair = blk * PPB + slot;
     const bool active = pair < npairs;
     const int lineA = active ? 2 * pair : 0;
     const int lineB = lineA + 1;
@@ -155,17 +277,7 @@ __global__ __launch_bounds__(256) void sweep_kernel(const Batch b) {
     double sA, sB;
     split_shift(betaA, bA, sA);
     split_shift(betaB, bB, sB);
-
-    // Weights of the pair, combined for the packed transform:
-    // wP = (wA + wB) / (2N), wQ = (wA - wB) / (2N) (1/N folds the inverse FFT scale).
-    for (int qi = t; qi < kTaps; qi += TPF) {
-        const int q = qi - kDMax;
-        const double wa = lagrange_weight(S.d, q, sA);
-        const double wb = lagrange_weight(S.d, q, sB);
-        const double sc = 0.5 / (double)N;
-        wsh[slot][0][qi] = (T)((wa + wb) * sc);
-        wsh[slot][1][qi] = (T)((wa - wb) * sc);
-    }
+    pair_weights<T, N, TPF>(S.d, sA, sB, t, wsh[slot][0], wsh[slot][1]);
 
     // Load the two lines packed as z = uA + i uB.
     cx<T> v[R];
@@ -175,94 +287,8 @@ __global__ __launch_bounds__(256) void sweep_kernel(const Batch b) {
         v[r] = active ? cx<T>{pA[j], pB[j]} : cx<T>{(T)0, (T)0};
     });
 
-    F::template run<-1>(v, t, lre, lim, tw);  // v[i] = Z[t + TPF kpos(i)]
-
-    // Symbol of the fractional-shift kernel for the modes m = t + k TPF:
-    //   S_m = sum_q w_q exp(2 pi i m q / N) = DFT_R^+ (H)[k],
-    //   H_c = sum_{q = c mod R} w_q exp(2 pi i t q / N).
-    // The packed product is Y_m = P_m Z_m + Q_m conj(Z_{N-m}) with P, Q the
-    // symbols of wP, wQ.
-    auto symbol = [&](int which, cx<T>(&H)[R]) {
-        cx<T> e[kEpsRow];
-        load_row<T, kEpsRow>(eps, e);
-        static_for<0, R>([&](auto cc) { H[decltype(cc)::value] = cx<T>{(T)0, (T)0}; });
-        static_for<0, kTaps>([&](auto qc) {
-            constexpr int qi = decltype(qc)::value;
-            constexpr int q = qi - kDMax;
-            constexpr int c = ((q % R) + R) % R;
-            constexpr int aq = q < 0 ? -q : q;
-            const T w = wsh[slot][which][qi];
-            if constexpr (q == 0) {
-                H[c].re += w;
-            } else if constexpr (q > 0) {
-                H[c].re = fma_t<T>(w, e[aq].re, H[c].re);
-                H[c].im = fma_t<T>(w, e[aq].im, H[c].im);
-            } else {
-                H[c].re = fma_t<T>(w, e[aq].re, H[c].re);
-                H[c].im = fma_t<T>(-w, e[aq].im, H[c].im);
-            }
-        });
-        dft<T, 1, R>(H);
-    };
-
     cx<T> Y[R];
-    if constexpr (TPF > 1) {
-        // Z to LDS at its natural position for the partner exchange.
-        __syncthreads();
-        const int pt = F::pad(t);
-        static_for<0, R>([&](auto ic) {
-            constexpr int i = decltype(ic)::value;
-            constexpr int C = TPF * F::kpos(i);
-            const int idx = (TPF % 16 == 0) ? F::template pad_add<C>(pt) : F::pad(t + C);
-            lre[idx] = v[i].re;
-            lim[idx] = v[i].im;
-        });
-        {
-            cx<T> H[R];
-            symbol(0, H);
-            static_for<0, R>([&](auto ic) {
-                constexpr int i = decltype(ic)::value;
-                constexpr int k = F::kpos(i);
-                Y[k] = cmul(H[k], v[i]);
-            });
-        }
-        __syncthreads();
-        {
-            cx<T> H[R];
-            symbol(1, H);
-            // partner index of m = t + k TPF is N - m = tp + (R - 1 - k) TPF for
-            // t > 0 (tp = TPF - t) and (R - k) TPF mod N for t = 0.
-            const int ptp = F::pad(TPF - t);
-            static_for<0, R>([&](auto kc) {
-                constexpr int k = decltype(kc)::value;
-                constexpr int C1 = (R - 1 - k) * TPF;
-                constexpr int C0 = ((R - k) % R) * TPF;
-                const int idx = t == 0 ? F::pad(C0)
-                                       : ((TPF % 16 == 0) ? F::template pad_add<C1>(ptp)
-                                                          : F::pad(TPF - t + C1));
-                const cx<T> Wk = cx<T>{lre[idx], -lim[idx]};
-                Y[k] = Y[k] + cmul(H[k], Wk);
-            });
-        }
-    } else {
-        __syncthreads();  // weights visible
-        cx<T> H[R];
-        symbol(0, H);
-        static_for<0, R>([&](auto ic) {
-            constexpr int i = decltype(ic)::value;
-            constexpr int k = F::kpos(i);
-            Y[k] = cmul(H[k], v[i]);
-        });
-        symbol(1, H);
-        static_for<0, R>([&](auto ic) {
-            constexpr int i = decltype(ic)::value;
-            constexpr int k = F::kpos(i);
-            constexpr int ip = F::kinv((N - k) & (N - 1));
-            Y[k] = Y[k] + cmul(H[k], cx<T>{v[ip].re, -v[ip].im});
-        });
-    }
-
-    F::template run<1>(Y, t, lre, lim, tw);  // Y[i] = y[t + TPF kpos(i)]
+    pair_transform<T, N, (sizeof(T) == 8)>(v, Y, t, lre, lim, tw, eps, wsh[slot][0], wsh[slot][1]);
 
     if (!active) return;
 
@@ -293,6 +319,160 @@ __global__ __launch_bounds__(256) void sweep_kernel(const Batch b) {
     });
 }
 
+// x-advection by dt = b.a[sim] directly on the v-fastest layout f[nx][nv]
+// (N = nx): a block owns the x-lines j0 .. j0 + B - 1, i.e. the tile
+// f[0..N)[j0..j0+B), staged through LDS with 16-byte row-segment loads and
+// stores, and runs the packed line-pair transform on B / 2 pairs at once.
+// Tiles are ordered so that the blocks sharing cache lines (neighbouring j0)
+// run on the same XCD at the same time.
+template <typename T, int N>
+struct Fused {
+    using F = Fft<T, N>;
+    static constexpr int TB = sizeof(T) == 4 ? (N >= 512 ? 1024 : 512) : (N >= 512 ? 512 : 256);
+    static constexpr int PPB = TB / F::TPF;     // line pairs per block
+    static constexpr int B = 2 * PPB;           // lines per block
+    static constexpr int VEC = 16 / sizeof(T);  // elements per 16-byte vector
+    static constexpr int VPR = B / VEC;         // vectors per tile row
+    static constexpr int SKEW = sizeof(T) == 4 ? (VPR >= 16 ? 1 : 16 / VPR) : 8;
+    static constexpr int LDSP = F::LDSN + SKEW; // per-array stride (bank skew)
+    static constexpr int ITER = N * VPR / TB;   // tile vectors per thread
+};
+
+template <typename T, int N>
+constexpr int kFusedThreads = Fused<T, N>::TB;
+
+template <typename T, int N>
+__global__ __launch_bounds__((kFusedThreads<T, N>)) void xsweep_fused_kernel(const Batch b) {
+    using F = Fft<T, N>;
+    using C = Fused<T, N>;
+    constexpr int R = F::R, TPF = F::TPF;
+    __shared__ T lds[C::PPB * 2 * C::LDSP];
+    __shared__ T wsh[C::PPB][2][kTaps];
+
+    const SimDev &S = *b.s[blockIdx.y];
+    const int nv = S.nv;
+    const int ntiles = nv / C::B;
+    const int hb = blockIdx.x;
+    if (hb >= ntiles) return;  // whole block idle
+    const int tile = (ntiles % 8 == 0) ? (hb % 8) * (ntiles / 8) + hb / 8 : hb;
+    const int j0 = tile * C::B;
+    T *f = (T *)S.f;
+    const int tid = threadIdx.x;
+
+    // Tile to LDS: column c of the tile is line j0 + c; pair c / 2 keeps line
+    // 2p in its real array and line 2p + 1 in its imaginary array.
+    static_for<0, C::ITER>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        const int q = tid + k * C::TB;
+        const int row = q / C::VPR, cv = q % C::VPR;
+        const T *src = f + (size_t)row * nv + j0 + cv * C::VEC;
+        T e[C::VEC];
+        if constexpr (sizeof(T) == 4) {
+            const float4 x = *reinterpret_cast<const float4 *>(src);
+            e[0] = x.x; e[1] = x.y; e[2] = x.z; e[3] = x.w;
+        } else {
+            const double2 x = *reinterpret_cast<const double2 *>(src);
+            e[0] = x.x; e[1] = x.y;
+        }
+        const int pr = F::pad(row);
+        static_for<0, C::VEC>([&](auto ec) {
+            constexpr int el = decltype(ec)::value;
+            const int c = cv * C::VEC + el;  // (c / 2) * 2 + c % 2 == c
+            lds[c * C::LDSP + pr] = e[el];
+        });
+    });
+
+    const int slot = tid / TPF;
+    const int t = tid % TPF;
+    T *lre = lds + (2 * slot) * C::LDSP;
+    T *lim = lre + C::LDSP;
+    const cx<T> *tw = (const cx<T> *)S.tw_x;
+    const cx<T> *eps = (const cx<T> *)S.eps_x + t * kEpsRow;
+    const int lineA = j0 + 2 * slot, lineB = lineA + 1;
+
+    const double dt = b.a[blockIdx.y];
+    long long bA, bB;
+    double sA, sB;
+    split_shift(-(S.vmin + lineA * S.dv) * dt * S.inv_dx, bA, sA);
+    split_shift(-(S.vmin + lineB * S.dv) * dt * S.inv_dx, bB, sB);
+    pair_weights<T, N, TPF>(S.d, sA, sB, t, wsh[slot][0], wsh[slot][1]);
+
+    __syncthreads();  // tile in LDS
+    cx<T> v[R];
+    {
+        const int pt = F::pad(t);
+        static_for<0, R>([&](auto rc) {
+            constexpr int r = decltype(rc)::value;
+            const int idx = F::template pad_add<r * TPF>(pt);
+            v[r] = cx<T>{lre[idx], lim[idx]};
+        });
+    }
+
+    cx<T> Y[R];
+    pair_transform<T, N, true>(v, Y, t, lre, lim, tw, eps, wsh[slot][0], wsh[slot][1]);
+
+    // Shifted result back to LDS: unshifted index j goes to position (j - b) mod N.
+    __syncthreads();
+    {
+        const int p0A = (t - (int)(bA & (N - 1))) & (N - 1);
+        const int p0B = (t - (int)(bB & (N - 1))) & (N - 1);
+        static_for<0, R>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            constexpr int i = F::kinv(k);
+            lre[F::pad((p0A + k * TPF) & (N - 1))] = Y[i].re;
+            lim[F::pad((p0B + k * TPF) & (N - 1))] = Y[i].im;
+        });
+    }
+    __syncthreads();
+
+    static_for<0, C::ITER>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        const int q = tid + k * C::TB;
+        const int row = q / C::VPR, cv = q % C::VPR;
+        T *dst = f + (size_t)row * nv + j0 + cv * C::VEC;
+        const int pr = F::pad(row);
+        T e[C::VEC];
+        static_for<0, C::VEC>([&](auto ec) {
+            constexpr int el = decltype(ec)::value;
+            e[el] = lds[(cv * C::VEC + el) * C::LDSP + pr];
+        });
+        if constexpr (sizeof(T) == 4) {
+            *reinterpret_cast<float4 *>(dst) = float4{e[0], e[1], e[2], e[3]};
+        } else {
+            *reinterpret_cast<double2 *>(dst) = double2{e[0], e[1]};
+        }
+    });
+}
+
+template <typename T, int N>
+static void launch_xsweep_fused(const Batch &b, int max_lines, hipStream_t st) {
+    using C = Fused<T, N>;
+    const int blocks = max_lines / C::B;
+    hipLaunchKernelGGL((xsweep_fused_kernel<T, N>), dim3(blocks, b.n), dim3(C::TB), 0, st, b);
+}
+
+template <typename T, int... L>
+static LaunchFn pick_fused(int logn, std::integer_sequence<int, L...>) {
+    LaunchFn fns[] = {&launch_xsweep_fused<T, (256 << L)>...};
+    return fns[logn - 8];
+}
+
+int fused_lines_per_block(bool fp64, int nx) {
+    const int logn = ilog2(nx);
+    if (nx < 256 || nx > VOG_MAX_N || (1 << logn) != nx) return 0;
+    constexpr int tf[5] = {Fused<float, 256>::B, Fused<float, 512>::B, Fused<float, 1024>::B,
+                           Fused<float, 2048>::B, Fused<float, 4096>::B};
+    constexpr int td[5] = {Fused<double, 256>::B, Fused<double, 512>::B, Fused<double, 1024>::B,
+                           Fused<double, 2048>::B, Fused<double, 4096>::B};
+    return fp64 ? td[logn - 8] : tf[logn - 8];
+}
+
+LaunchFn fused_xsweep_launcher(bool fp64, int nx) {
+    if (fused_lines_per_block(fp64, nx) == 0) return nullptr;
+    using Seq = std::make_integer_sequence<int, 5>;
+    return fp64 ? pick_fused<double>(ilog2(nx), Seq{}) : pick_fused<float>(ilog2(nx), Seq{});
+}
+
 template <typename T, int N, int KIND>
 static void launch_sweep(const Batch &b, int max_lines, hipStream_t st) {
     constexpr int PPB = 256 / Fft<T, N>::TPF;
@@ -313,6 +493,7 @@ LaunchFn sweep_launcher(bool fp64, int n, bool vsweep) {
     if (fp64) return vsweep ? pick_sweep<double, 0>(logn, Seq{}) : pick_sweep<double, 1>(logn, Seq{});
     return vsweep ? pick_sweep<float, 0>(logn, Seq{}) : pick_sweep<float, 1>(logn, Seq{});
 }
+
 
 // ----------------------------------------------------------------- transpose
 

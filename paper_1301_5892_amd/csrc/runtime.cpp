@@ -74,6 +74,18 @@ struct Layout {
     size_t f, g, E, part, rho, mom, tw_x, tw_v, eps_x, eps_v, tw_x64, feq_g, feq64, ring, dev, total;
 };
 
+// How the x-sweep reaches the x-lines of the v-fastest array f[nx][nv]:
+// tiles of whole x-lines staged through LDS when a tile fits the grid,
+// otherwise a transposed copy.
+enum XMode { X_TRANSPOSED = 0, X_TILED = 1 };
+
+XMode xsweep_mode(const vog_config &c) {
+    const int B = fused_lines_per_block(c.precision != VOG_FP32_DELTAF, c.nx);
+    return (B > 0 && c.nv >= B) ? X_TILED : X_TRANSPOSED;
+}
+
+bool uses_fused_xsweep(const vog_config &c) { return xsweep_mode(c) != X_TRANSPOSED; }
+
 Layout layout_of(const vog_config &c) {
     const size_t es = c.precision == VOG_FP32_DELTAF ? 4 : 8;
     const size_t cells = (size_t)c.nx * c.nv;
@@ -86,7 +98,7 @@ Layout layout_of(const vog_config &c) {
         return at;
     };
     L.f = take(cells * es);
-    L.g = take(cells * es);
+    L.g = take(uses_fused_xsweep(c) ? 0 : cells * es);
     L.E = take(sizeof(double) * c.nx);
     L.part = take(sizeof(double) * c.nx * (size_t)nparts);
     L.rho = take(sizeof(double) * c.nx);
@@ -124,6 +136,8 @@ struct vog_sim {
     double t;
     int64_t diag_read;     // records consumed by vog_get_diag
     bool fp64;
+    bool fused;            // x-sweep directly on the v-fastest layout
+    int xmode;             // XMode
     // profiling
     bool prof;
     std::vector<EventPair> ev[VOG_NUM_KINDS];
@@ -284,18 +298,27 @@ int check_launch() {
     return VOG_OK;
 }
 
-// v-sweeps of all sims (tau per sim).
+// Sweeps of all sims (tau or dt per sim).  vsweep: v-advection on the
+// v-fastest layout.  Otherwise x-advection: fused = true selects the sims
+// whose x-sweep runs on the v-fastest layout, fused = false the others (which
+// work on the transposed copy).
 int run_sweep(vog_sim *lead, const std::vector<vog_sim *> &sims, const std::vector<double> &arg,
-              bool vsweep) {
+              bool vsweep, bool fused = false) {
     std::map<std::pair<int, int>, Group> groups;  // (fp64, line length)
     for (size_t k = 0; k < sims.size(); ++k) {
         vog_sim *s = sims[k];
-        auto key = std::make_pair((int)s->fp64, vsweep ? s->cfg.nv : s->cfg.nx);
+        if (!vsweep && s->fused != fused) continue;
+        // key: (precision and x-sweep mode, line length)
+        auto key = std::make_pair((int)s->fp64 + 2 * (vsweep ? 0 : s->xmode), vsweep ? s->cfg.nv : s->cfg.nx);
         groups[key].sims.push_back(s);
         groups[key].arg.push_back(arg[k]);
     }
     for (auto &kv : groups) {
-        LaunchFn fn = sweep_launcher(kv.first.first != 0, kv.first.second, vsweep);
+        const bool fp64 = (kv.first.first & 1) != 0;
+        const int xmode = kv.first.first / 2;
+        LaunchFn fn = vsweep             ? sweep_launcher(fp64, kv.first.second, true)
+                      : xmode == X_TILED ? fused_xsweep_launcher(fp64, kv.first.second)
+                                         : sweep_launcher(fp64, kv.first.second, false);
         if (!fn) return fail(VOG_EINVAL, "no sweep kernel for this line length");
         int rc = for_chunks(kv.second, [&](const Batch &b, size_t base) {
             int maxl = 0;
@@ -316,7 +339,8 @@ int run_sweep(vog_sim *lead, const std::vector<vog_sim *> &sims, const std::vect
 
 int run_transpose(vog_sim *lead, const std::vector<vog_sim *> &sims, bool to_v) {
     std::map<int, Group> groups;
-    for (vog_sim *s : sims) groups[(int)s->fp64].sims.push_back(s);
+    for (vog_sim *s : sims)
+        if (!s->fused) groups[(int)s->fp64].sims.push_back(s);
     for (auto &kv : groups) {
         int rc = for_chunks(kv.second, [&](const Batch &b, size_t base) {
             int maxt = 0;
@@ -339,7 +363,8 @@ int run_transpose(vog_sim *lead, const std::vector<vog_sim *> &sims, bool to_v) 
 // rho from the partial sums of the x->v transpose.
 int run_rho_reduce(vog_sim *lead, const std::vector<vog_sim *> &sims) {
     Group g;
-    g.sims = sims;
+    for (vog_sim *s : sims)
+        if (!s->fused) g.sims.push_back(s);
     return for_chunks(g, [&](const Batch &b, size_t base) {
         int maxnx = 0;
         for (int k = 0; k < b.n; ++k) maxnx = std::max(maxnx, g.sims[base + k]->cfg.nx);
@@ -380,6 +405,7 @@ int run_field(vog_sim *lead, const std::vector<vog_sim *> &sims, const std::vect
     return VOG_OK;
 }
 
+// rho = int f dv straight from the v-fastest layout.
 int run_rho_v(vog_sim *lead, const std::vector<vog_sim *> &sims) {
     std::map<int, Group> groups;
     for (vog_sim *s : sims) groups[(int)s->fp64].sims.push_back(s);
@@ -387,7 +413,10 @@ int run_rho_v(vog_sim *lead, const std::vector<vog_sim *> &sims) {
         int rc = for_chunks(kv.second, [&](const Batch &b, size_t base) {
             int maxnx = 0;
             for (int k = 0; k < b.n; ++k) maxnx = std::max(maxnx, kv.second.sims[base + k]->cfg.nx);
+            EventPair *p;
+            prof_begin(lead, K_RHO, &p);
             launch_rho_v(kv.first != 0, b, maxnx, lead->stream);
+            prof_end(lead, p);
             return check_launch();
         });
         if (rc != VOG_OK) return rc;
@@ -432,6 +461,23 @@ int field_from_f(vog_sim *s) {
     return run_field(s, one, st, tt);
 }
 
+// x-advection of all sims by dt; with_rho also leaves rho = int f dv.
+int x_advection(vog_sim *lead, const std::vector<vog_sim *> &sims, const std::vector<double> &dt,
+                bool with_rho) {
+    int rc;
+    std::vector<vog_sim *> fused;
+    for (vog_sim *s : sims)
+        if (s->fused) fused.push_back(s);
+    if ((rc = run_sweep(lead, sims, dt, false, true)) != VOG_OK) return rc;
+    if ((rc = run_transpose(lead, sims, false)) != VOG_OK) return rc;
+    if ((rc = run_sweep(lead, sims, dt, false, false)) != VOG_OK) return rc;
+    if ((rc = run_transpose(lead, sims, true)) != VOG_OK) return rc;
+    if (!with_rho) return VOG_OK;
+    if ((rc = run_rho_reduce(lead, sims)) != VOG_OK) return rc;
+    if (!fused.empty() && (rc = run_rho_v(lead, fused)) != VOG_OK) return rc;
+    return VOG_OK;
+}
+
 int device_guard(vog_sim *s) {
     int cur = -1;
     HIP_TRY(hipGetDevice(&cur));
@@ -452,10 +498,7 @@ int step_sims(const std::vector<vog_sim *> &sims, const std::vector<double> &dt,
         }
         int rc;
         if ((rc = run_sweep(lead, sims, tau, true)) != VOG_OK) return rc;
-        if ((rc = run_transpose(lead, sims, false)) != VOG_OK) return rc;
-        if ((rc = run_sweep(lead, sims, dt, false)) != VOG_OK) return rc;
-        if ((rc = run_transpose(lead, sims, true)) != VOG_OK) return rc;
-        if ((rc = run_rho_reduce(lead, sims)) != VOG_OK) return rc;
+        if ((rc = x_advection(lead, sims, dt, true)) != VOG_OK) return rc;
         if ((rc = run_field(lead, sims, stepno, tnow)) != VOG_OK) return rc;
         if ((rc = run_sweep(lead, sims, tau, true)) != VOG_OK) return rc;
         std::vector<vog_sim *> msims;
@@ -522,6 +565,8 @@ int vog_create(const vog_config *c, void *dev_workspace, size_t bytes, void *hip
     s->lay = L;
     s->stream = (hipStream_t)hip_stream;
     s->fp64 = c->precision != VOG_FP32_DELTAF;
+    s->fused = uses_fused_xsweep(*c);
+    s->xmode = xsweep_mode(*c);
     s->step = 0;
     s->t = 0.0;
     s->diag_read = 0;
@@ -555,7 +600,7 @@ int vog_create(const vog_config *c, void *dev_workspace, size_t bytes, void *hip
     SimDev &D = s->host_dev;
     memset(&D, 0, sizeof(D));
     D.f = s->ws + L.f;
-    D.g = s->ws + L.g;
+    D.g = s->fused ? nullptr : s->ws + L.g;
     D.E = (double *)(s->ws + L.E);
     D.part = (double *)(s->ws + L.part);
     D.rho = (double *)(s->ws + L.rho);
@@ -769,11 +814,7 @@ int vog_sweep(vog_sim *s, int which, double arg) {
     std::vector<vog_sim *> one{s};
     std::vector<double> a{arg};
     if (which == 0) return run_sweep(s, one, a, true);
-    if (which == 1) {
-        if ((rc = run_transpose(s, one, false)) != VOG_OK) return rc;
-        if ((rc = run_sweep(s, one, a, false)) != VOG_OK) return rc;
-        return run_transpose(s, one, true);
-    }
+    if (which == 1) return x_advection(s, one, a, false);
     return field_from_f(s);
 }
 
@@ -910,7 +951,7 @@ int vog_profile_read(vog_sim *s, double *ms, int64_t *launches, int nkinds) {
 
 const char *vog_build_info(void) {
     return "libvog gfx950: radix-16 Stockham LDS FFT, paired real lines, integer-shift store, "
-           "separate tiled transposes";
+           "x-sweep on the v-fastest layout (XCD-ordered line tiles), rho row sums";
 }
 
 }  // extern "C"

@@ -53,6 +53,9 @@ enum Kind { K_SWEEP_V = 0, K_SWEEP_X = 1, K_T_VX = 2, K_T_XV = 3, K_FIELD = 4, K
 // Host-side launchers (defined in kernels.hip).
 using LaunchFn = void (*)(const Batch &, int max_lines, hipStream_t);
 LaunchFn sweep_launcher(bool fp64, int n, bool vsweep);
+// x-sweep on the v-fastest layout: lines per block (0 if not available) and launcher.
+int fused_lines_per_block(bool fp64, int nx);
+LaunchFn fused_xsweep_launcher(bool fp64, int nx);
 void launch_transpose(bool fp64, bool to_v, const Batch &b, int max_tiles, hipStream_t st);
 LaunchFn field_launcher(int nx);
 void launch_rho_v(bool fp64, const Batch &b, int max_nx, hipStream_t st);

@@ -53,7 +53,7 @@ def test_named_workloads_validate(vog, w):
     assert vog.load().vog_config_validate(ctypes.byref(c)) == 0
     es = 4 if w.precision == "fp32_deltaf" else 8
     nb = vog.workspace_bytes(c)
-    assert nb >= 2 * w.nx * w.nv * es
+    assert nb >= w.nx * w.nv * es
     assert nb < 2 * w.nx * w.nv * es + (4 << 20)
 
 

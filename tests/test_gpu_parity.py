@@ -36,8 +36,12 @@ def stored(o):
 
 # ---------------------------------------------------------------- single sweeps
 
+# Covers both x-sweep layouts: nx >= 256 with nv at least one tile of whole
+# x-lines runs on the v-fastest layout (tiles of 4..128 lines), smaller grids
+# go through the transposed copy.
 SWEEP_GRIDS = [(8, 8, 7), (16, 32, 15), (32, 64, 17), (64, 128, 17), (256, 64, 17),
-               (64, 1024, 17), (128, 4096, 17), (4096, 16, 9), (512, 512, 3), (32, 32, 1)]
+               (64, 1024, 17), (128, 4096, 17), (4096, 16, 9), (512, 512, 3), (32, 32, 1),
+               (4096, 8, 7), (2048, 16, 15), (256, 16, 15), (1024, 2048, 17)]
 
 
 @pytest.mark.parametrize("nx,nv,deg", SWEEP_GRIDS, ids=lambda x: str(x))
@@ -50,6 +54,20 @@ def test_x_sweep_fp64(gpu, nx, nv, deg, dt):
     s.advect_x(dt)
     o.advect_x(dt)
     assert rel(s.get_f(), o.f) < TOL64
+
+
+@pytest.mark.parametrize("nx,nv", [(4096, 8), (4096, 64), (2048, 16), (1024, 64), (512, 256),
+                                   (256, 512), (256, 32), (64, 128), (128, 16)])
+@pytest.mark.parametrize("dt", [0.1, -2.3])
+def test_x_sweep_fp32_deltaf(gpu, nx, nv, dt):
+    deg = min(17, nv - 1)
+    w = workloads.landau_strong().replace(nx=nx, nv=nv, degree=deg, amp=(0.3, 0.1),
+                                           kx=(0.5, 1.5), phase=(0.2, 1.0))
+    s = sim_of(gpu, w).init()
+    o = oracle.Oracle(w).init()
+    s.advect_x(dt)
+    o.advect_x(dt)
+    assert rel(s.get_raw(), o.f) < TOL32
 
 
 @pytest.mark.parametrize("nx,nv,deg", SWEEP_GRIDS, ids=lambda x: str(x))
