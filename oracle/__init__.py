@@ -44,7 +44,12 @@ class _Cfg(ctypes.Structure):
                 ("degree", ctypes.c_int), ("deltaf", ctypes.c_int), ("field_zero", ctypes.c_int),
                 ("n_feq", ctypes.c_int),
                 ("feq_a", ctypes.c_double * MAX_FEQ), ("feq_c", ctypes.c_double * MAX_FEQ),
-                ("feq_sigma", ctypes.c_double * MAX_FEQ)]
+                ("feq_sigma", ctypes.c_double * MAX_FEQ),
+                ("poisson", ctypes.c_int), ("zero_mean", ctypes.c_int),
+                ("drive_emax", ctypes.c_double), ("drive_k", ctypes.c_double),
+                ("drive_omega", ctypes.c_double), ("drive_t0", ctypes.c_double),
+                ("drive_tl", ctypes.c_double), ("drive_tr", ctypes.c_double),
+                ("drive_twl", ctypes.c_double), ("drive_twr", ctypes.c_double)]
 
 
 _lib = None
@@ -69,9 +74,15 @@ def lib():
         L.orc_advect_v.argtypes = [cp, _D, ctypes.c_double, _D, _D]
         L.orc_rho.argtypes = [cp, _D, _D]
         L.orc_poisson.argtypes = [cp, _D, _D]
+        L.orc_solve.argtypes = [cp, _D, _D]
         L.orc_field.argtypes = [cp, _D, _D, _D]
-        L.orc_step.argtypes = [cp, ctypes.c_double, _D, _D, _D, _D]
-        L.orc_run.argtypes = [cp, ctypes.c_double, ctypes.c_int, _D, _D, _D]
+        L.orc_step.argtypes = [cp, ctypes.c_double, ctypes.c_double, _D, _D, _D, _D]
+        L.orc_run.argtypes = [cp, ctypes.c_double, ctypes.c_double, ctypes.c_int, _D, _D, _D]
+        L.orc_drive_amplitude.argtypes = [cp, ctypes.c_double]
+        L.orc_drive_amplitude.restype = ctypes.c_double
+        L.orc_drive.argtypes = [cp, ctypes.c_double, ctypes.c_double]
+        L.orc_drive.restype = ctypes.c_double
+        L.orc_rho_modes.argtypes = [cp, _D, ctypes.c_int, _D]
         L.orc_diag_field.argtypes = [cp, _D, _D, _D]
         L.orc_diag_moments.argtypes = [cp, _D, _D, _D]
         L.orc_num_threads.restype = ctypes.c_int
@@ -141,6 +152,13 @@ class Oracle:
         c.n_feq = len(w.feq_a)
         for g in range(c.n_feq):
             c.feq_a[g], c.feq_c[g], c.feq_sigma[g] = w.feq_a[g], w.feq_c[g], w.feq_sigma[g]
+        c.poisson = 1 if w.poisson == "trapezoid" else 0
+        c.zero_mean = int(bool(w.zero_mean))
+        if w.drive is not None:
+            d = w.drive
+            c.drive_emax, c.drive_k, c.drive_omega = d.emax, d.k, d.omega
+            c.drive_t0, c.drive_tl, c.drive_tr = d.t0, d.tl, d.tr
+            c.drive_twl, c.drive_twr = d.twl, d.twr
         self.cfg = c
         self.deltaf = bool(deltaf)
         self.f = np.zeros((w.nx, w.nv))
@@ -209,9 +227,10 @@ class Oracle:
         return rho
 
     def poisson(self, rho: np.ndarray) -> np.ndarray:
+        """E from rho with the workload's field solve (Fourier or trapezoid)."""
         rho = np.ascontiguousarray(rho, dtype=np.float64)
         E = np.zeros(self.w.nx)
-        lib().orc_poisson(ctypes.byref(self.cfg), _p(rho), _p(E))
+        lib().orc_solve(ctypes.byref(self.cfg), _p(rho), _p(E))
         return E
 
     def step(self, nsteps: int = 1, dt: Optional[float] = None) -> np.ndarray:
@@ -219,8 +238,8 @@ class Oracle:
         ||E||_2, rho_hat_0, |rho_hat_1| after each step."""
         dt = self.w.dt if dt is None else dt
         diag = np.zeros((nsteps, 3))
-        lib().orc_run(ctypes.byref(self.cfg), float(dt), int(nsteps), _p(self.f), _p(self.E),
-                      _p(diag))
+        lib().orc_run(ctypes.byref(self.cfg), float(self.t), float(dt), int(nsteps), _p(self.f),
+                      _p(self.E), _p(diag))
         self.step_count += nsteps
         self.t += nsteps * dt
         if nsteps:
@@ -231,6 +250,17 @@ class Oracle:
         out = np.zeros(3)
         lib().orc_diag_field(ctypes.byref(self.cfg), _p(self.rho), _p(self.E), _p(out))
         return out
+
+    def rho_modes(self, nmodes: int = 7) -> np.ndarray:
+        out = np.zeros(nmodes)
+        lib().orc_rho_modes(ctypes.byref(self.cfg), _p(self.rho), int(nmodes), _p(out))
+        return out
+
+    def drive_amplitude(self, t: float) -> float:
+        return lib().orc_drive_amplitude(ctypes.byref(self.cfg), float(t))
+
+    def drive(self, t: float, x: float) -> float:
+        return lib().orc_drive(ctypes.byref(self.cfg), float(t), float(x))
 
     def diag_moments(self) -> np.ndarray:
         out = np.zeros(2)

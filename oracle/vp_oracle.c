@@ -21,6 +21,9 @@
  *     gives a zero-mean E.  The Nyquist mode is also set to zero.
  *   - Diagnostics of Section 4: ||E||_2, the mass rho_hat_0, |rho_hat_1|,
  *     the L2 norm of f and the total energy.
+ *   - Variants: the trapezoidal field solve with or without the zero-mean
+ *     modification (Section 3.2), and the external drive of the KEEN-wave
+ *     test (Section 4.3), which enters the v-advection as E - E_app.
  */
 #include "vp_oracle.h"
 
@@ -236,23 +239,104 @@ void orc_poisson(const orc_cfg *c, const double *rho, double *E) {
     free(Er);
 }
 
-void orc_field(const orc_cfg *c, const double *f, double *E, double *rho) {
-    orc_rho(c, f, rho);
+/* Trapezoidal field solve (Section 3.2): rho~ = rho - mean(rho) (zero_mean)
+ * or rho - 1; E~_0 = 0, E~_{k+1} = E~_k + dx (rho~_k + rho~_{k+1}) / 2 for
+ * k = 0 .. nx-2; with zero_mean, E = E~ - mean(E~), else E = E~. */
+static void poisson_trapezoid(const orc_cfg *c, const double *rho, double *E) {
+    const int n = c->nx;
+    const double dx = dx_of(c);
+    double mean = 1.0;
+    if (c->zero_mean) {
+        mean = 0.0;
+        for (int i = 0; i < n; ++i) mean += rho[i];
+        mean /= n;
+    }
+    E[0] = 0.0;
+    for (int k = 0; k + 1 < n; ++k)
+        E[k + 1] = E[k] + dx * 0.5 * ((rho[k] - mean) + (rho[k + 1] - mean));
+    if (c->zero_mean) {
+        double em = 0.0;
+        for (int i = 0; i < n; ++i) em += E[i];
+        em /= n;
+        for (int i = 0; i < n; ++i) E[i] -= em;
+    }
+}
+
+/* E from rho with the configured solve (zero for free streaming). */
+void orc_solve(const orc_cfg *c, const double *rho, double *E) {
     if (c->field_zero)
         for (int i = 0; i < c->nx; ++i) E[i] = 0.0;
+    else if (c->poisson == 1)
+        poisson_trapezoid(c, rho, E);
     else
         orc_poisson(c, rho, E);
 }
 
-/* One Strang step (Section 1.1).  f, E hold f^n, E^n on entry and f^{n+1},
- * E^{n+1} on exit; rho receives the density the new field was solved from;
- * tmp has nx*nv doubles. */
-void orc_step(const orc_cfg *c, double dt, double *f, double *E, double *rho, double *tmp) {
+void orc_field(const orc_cfg *c, const double *f, double *E, double *rho) {
+    orc_rho(c, f, rho);
+    orc_solve(c, rho, E);
+}
+
+/* Drive envelope (Section 4.3):
+ * a(t) = (0.5 (tanh((t - tL)/twL) - tanh((t - tR)/twR)) - eps) / (1 - eps),
+ * eps the same bracket at t0, so that a(t0) = 0. */
+double orc_drive_amplitude(const orc_cfg *c, double t) {
+    double eps = 0.5 * (tanh((c->drive_t0 - c->drive_tl) / c->drive_twl) -
+                        tanh((c->drive_t0 - c->drive_tr) / c->drive_twr));
+    double br = 0.5 * (tanh((t - c->drive_tl) / c->drive_twl) - tanh((t - c->drive_tr) / c->drive_twr));
+    return (br - eps) / (1.0 - eps);
+}
+
+/* E_app(t, x) = emax k a(t) sin(k x - omega t). */
+double orc_drive(const orc_cfg *c, double t, double x) {
+    if (c->drive_emax == 0.0) return 0.0;
+    return c->drive_emax * c->drive_k * orc_drive_amplitude(c, t) *
+           sin(c->drive_k * x - c->drive_omega * t);
+}
+
+/* |rho_hat_m| for m = 1 .. nmodes, rho_hat_m = (1/nx) sum_i rho_i e^{-2 pi i m i / nx}. */
+void orc_rho_modes(const orc_cfg *c, const double *rho, int nmodes, double *abs_modes) {
+    const int n = c->nx;
+    for (int m = 1; m <= nmodes; ++m) {
+        double re = 0.0, im = 0.0;
+        for (int i = 0; i < n; ++i) {
+            long k = ((long)m * i) % n;
+            re += rho[i] * cos(2.0 * ORC_PI * k / n);
+            im -= rho[i] * sin(2.0 * ORC_PI * k / n);
+        }
+        abs_modes[m - 1] = sqrt(re * re + im * im) / n;
+    }
+}
+
+/* v-advection with the field E - E_app(t, x_i). */
+static void advect_v_driven(const orc_cfg *c, const double *E, double t, double tau,
+                            const double *f, double *out, double *Etot) {
+    for (int i = 0; i < c->nx; ++i)
+        Etot[i] = (c->field_zero ? 0.0 : E[i]) - orc_drive(c, t, x_of(c, i));
+    orc_cfg cc = *c;
+    cc.field_zero = 0;
+    orc_advect_v(&cc, Etot, tau, f, out);
+}
+
+/* One Strang step (Section 1.1) from time t.  f, E hold f^n, E^n on entry
+ * and f^{n+1}, E^{n+1} on exit; rho receives the density the new field was
+ * solved from; tmp has nx*nv doubles.  With a drive, the first half step
+ * uses E^n - E_app(t^n) and the second E^{n+1} - E_app(t^{n+1}). */
+void orc_step(const orc_cfg *c, double t, double dt, double *f, double *E, double *rho, double *tmp) {
     const long cells = (long)c->nx * c->nv;
-    orc_advect_v(c, E, 0.5 * dt, f, tmp);
-    orc_advect_x(c, dt, tmp, f);
-    orc_field(c, f, E, rho);
-    orc_advect_v(c, E, 0.5 * dt, f, tmp);
+    if (c->drive_emax != 0.0) {
+        double *Etot = (double *)malloc(sizeof(double) * c->nx);
+        advect_v_driven(c, E, t, 0.5 * dt, f, tmp, Etot);
+        orc_advect_x(c, dt, tmp, f);
+        orc_field(c, f, E, rho);
+        advect_v_driven(c, E, t + dt, 0.5 * dt, f, tmp, Etot);
+        free(Etot);
+    } else {
+        orc_advect_v(c, E, 0.5 * dt, f, tmp);
+        orc_advect_x(c, dt, tmp, f);
+        orc_field(c, f, E, rho);
+        orc_advect_v(c, E, 0.5 * dt, f, tmp);
+    }
     memcpy(f, tmp, sizeof(double) * cells);
 }
 
@@ -290,14 +374,14 @@ void orc_diag_moments(const orc_cfg *c, const double *f, const double *E, double
     out2[1] = 0.5 * dx * dv * ek + 0.5 * dx * ee;
 }
 
-/* nsteps Strang steps; diag (3 doubles per step, may be NULL) receives
- * ||E^{n+1}||_2, rho_hat_0 and |rho_hat_1| after each step. */
-void orc_run(const orc_cfg *c, double dt, int nsteps, double *f, double *E, double *diag) {
+/* nsteps Strang steps from time t0; diag (3 doubles per step, may be NULL)
+ * receives ||E^{n+1}||_2, rho_hat_0 and |rho_hat_1| after each step. */
+void orc_run(const orc_cfg *c, double t0, double dt, int nsteps, double *f, double *E, double *diag) {
     const long cells = (long)c->nx * c->nv;
     double *tmp = (double *)malloc(sizeof(double) * cells);
     double *rho = (double *)malloc(sizeof(double) * c->nx);
     for (int n = 0; n < nsteps; ++n) {
-        orc_step(c, dt, f, E, rho, tmp);
+        orc_step(c, t0 + n * dt, dt, f, E, rho, tmp);
         if (diag) orc_diag_field(c, rho, E, diag + 3L * n);
     }
     free(tmp);

@@ -32,6 +32,11 @@ typedef struct {
     int field_zero;    /* 1: E is held at zero (free streaming) */
     int n_feq;
     double feq_a[ORC_MAX_FEQ], feq_c[ORC_MAX_FEQ], feq_sigma[ORC_MAX_FEQ];
+    int poisson;       /* 0: Fourier; 1: trapezoidal rule */
+    int zero_mean;     /* trapezoidal only: 1 subtracts mean(rho) and mean(E) */
+    /* external drive E_app(t, x) = emax k a(t) sin(k x - omega t) (Section 4.3);
+     * emax = 0 switches it off */
+    double drive_emax, drive_k, drive_omega, drive_t0, drive_tl, drive_tr, drive_twl, drive_twr;
 } orc_cfg;
 
 int orc_num_threads(void);
@@ -50,10 +55,14 @@ void orc_advect_x(const orc_cfg *c, double dt, const double *f, double *out);
 void orc_advect_v(const orc_cfg *c, const double *E, double tau, const double *f, double *out);
 void orc_rho(const orc_cfg *c, const double *f, double *rho);
 void orc_poisson(const orc_cfg *c, const double *rho, double *E);
+void orc_solve(const orc_cfg *c, const double *rho, double *E);
 void orc_field(const orc_cfg *c, const double *f, double *E, double *rho);
 
-void orc_step(const orc_cfg *c, double dt, double *f, double *E, double *rho, double *tmp);
-void orc_run(const orc_cfg *c, double dt, int nsteps, double *f, double *E, double *diag);
+double orc_drive_amplitude(const orc_cfg *c, double t);
+double orc_drive(const orc_cfg *c, double t, double x);
+void orc_step(const orc_cfg *c, double t, double dt, double *f, double *E, double *rho, double *tmp);
+void orc_run(const orc_cfg *c, double t0, double dt, int nsteps, double *f, double *E, double *diag);
+void orc_rho_modes(const orc_cfg *c, const double *rho, int nmodes, double *abs_modes);
 
 void orc_diag_field(const orc_cfg *c, const double *rho, const double *E, double *out3);
 void orc_diag_moments(const orc_cfg *c, const double *f, const double *E, double *out2);

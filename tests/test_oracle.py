@@ -271,3 +271,79 @@ def test_landau_mass_and_field_history(orc):
     d = o.step(30)
     assert np.all(np.abs(d[:, 1] - d[0, 1]) < 1e-14)        # mass drift
     assert np.all(d[:, 0] > 0) and d[-1, 0] < d[0, 0]        # damping
+
+
+# ------------------------------------------------------------------ variants
+
+def _trap(w, zero_mean=True):
+    return w.replace(poisson="trapezoid", zero_mean=zero_mean)
+
+
+def test_trapezoid_field_converges_to_fourier(orc):
+    # The trapezoidal integral of a smooth periodic rho approaches the exact
+    # (Fourier) field at second order in dx (Section 3.2).
+    errs = []
+    for nx in (32, 64, 128):
+        w = workloads.landau_weak().replace(nx=nx, nv=64, degree=17)
+        o, ot = orc.Oracle(w), orc.Oracle(_trap(w))
+        x = o.x()
+        rho = 1.0 + 0.3 * np.cos(0.5 * x) + 0.1 * np.sin(1.5 * x)
+        errs.append(np.max(np.abs(ot.poisson(rho) - o.poisson(rho))))
+    assert errs[0] / errs[1] > 3.5 and errs[1] / errs[2] > 3.5, errs
+
+
+def test_trapezoid_without_zero_mean(orc):
+    # rho - 1 integrated from E_0 = 0: for rho = 1 + a cos(kx) the field is
+    # (a/k) sin(kx) up to O(dx^2) and keeps the integration constant; the
+    # zero-mean variant is the same field minus its mean.
+    w = workloads.landau_weak().replace(nx=128)
+    o0, o1 = orc.Oracle(_trap(w, False)), orc.Oracle(_trap(w, True))
+    x = o0.x()
+    rho = 1.0 + 0.2 * np.cos(0.5 * x)
+    E0, E1 = o0.poisson(rho), o1.poisson(rho)
+    assert E0[0] == 0.0
+    assert np.max(np.abs(E0 - 0.2 / 0.5 * np.sin(0.5 * x))) < 2e-3
+    assert np.max(np.abs(E1 - (E0 - E0.mean()))) < 1e-13
+    # a wrong background shows up only without the zero-mean step
+    E0b, E1b = o0.poisson(rho + 0.01), o1.poisson(rho + 0.01)
+    assert np.max(np.abs(E1b - E1)) < 1e-14
+    assert np.max(np.abs(E0b - E0)) > 0.05
+
+
+def test_drive_envelope(orc):
+    # a(t0) = 0, a ~ 1 between the ramps, a -> 0 after t_R (Section 4.3).
+    o = orc.Oracle(workloads.keen(64, 0.1, 10))
+    assert abs(o.drive_amplitude(0.0)) < 1e-15
+    assert abs(o.drive_amplitude(188.0) - 1.0) < 1e-4
+    # after t_R the bracket vanishes and a -> -eps / (1 - eps), eps ~ 1.0e-3
+    eps = 0.5 * (math.tanh(-69.0 / 20.0) - math.tanh(-307.0 / 20.0))
+    assert abs(o.drive_amplitude(1000.0) + eps / (1.0 - eps)) < 1e-9
+    assert 0.4 < o.drive_amplitude(69.0) < 0.6
+    # E_app = emax k a(t) sin(k x - omega t)
+    t, x = 150.0, 3.0
+    assert abs(o.drive(t, x) - 0.2 * 0.26 * o.drive_amplitude(t) * math.sin(0.26 * x - 0.37 * t)) < 1e-15
+
+
+def test_drive_enters_the_v_shift(orc):
+    # No self-consistent field, delta f = 0 at t = 0 where a(0) = 0: after one
+    # step delta f = f_eq(v + dt/2 E_app(dt, x)) - f_eq(v), i.e. the second
+    # half step moves the foot by -dt/2 (E - E_app) with E = 0 at t = dt.
+    d = workloads.Drive(emax=5.0, tl=0.05, twl=0.01, tr=1e9, twr=1.0, t0=0.0)
+    w = workloads.keen(64, 0.1, 1).replace(nv=128, field="zero", drive=d, precision="fp64_deltaf")
+    o = orc.Oracle(w).init()
+    o.step(1)
+    x, v = o.x()[:, None], o.v()[None, :]
+    Eapp = np.array([o.drive(w.dt, xi) for xi in o.x()])[:, None]
+    fm = lambda vv: np.exp(-vv ** 2 / 2) / math.sqrt(2 * math.pi)
+    assert np.max(np.abs(Eapp)) > 0.5
+    assert np.max(np.abs(o.f - (fm(v + 0.5 * w.dt * Eapp) - fm(v)))) < 1e-13
+
+
+def test_rho_modes_normalisation(orc):
+    # rho_hat_m = (1/nx) sum rho_i e^{-2 pi i m i/nx}: equals numpy's FFT / nx.
+    w = workloads.landau_weak()
+    o = orc.Oracle(w)
+    rng = np.random.default_rng(2)
+    o.rho = rng.standard_normal(w.nx)
+    ref = np.abs(np.fft.fft(o.rho))[1:8] / w.nx
+    assert np.allclose(o.rho_modes(7), ref, rtol=0, atol=1e-14)

@@ -30,6 +30,20 @@ PRECISIONS = ("fp64_plain", "fp32_deltaf", "fp64_deltaf")
 
 
 @dataclasses.dataclass(frozen=True)
+class Drive:
+    """External drive E_app(t, x) = emax k a(t) sin(k x - omega t) of the
+    KEEN-wave test (Section 4.3), envelope a(t) from t0, tl, tr, twl, twr."""
+    emax: float = 0.2
+    k: float = 0.26
+    omega: float = 0.37
+    t0: float = 0.0
+    tl: float = 69.0
+    tr: float = 307.0
+    twl: float = 20.0
+    twr: float = 20.0
+
+
+@dataclasses.dataclass(frozen=True)
 class Workload:
     name: str
     nx: int
@@ -48,6 +62,9 @@ class Workload:
     kx: Tuple[float, ...]
     phase: Tuple[float, ...]
     field: str = "self_consistent"  # or "zero" (free streaming)
+    poisson: str = "fourier"        # or "trapezoid"
+    zero_mean: bool = True          # trapezoid only
+    drive: Optional[Drive] = None
 
     @property
     def cells(self) -> int:
@@ -95,6 +112,15 @@ def large_grid() -> Workload:
                     0.02, 500, "fp32_deltaf",
                     amp=(1e-3,) * 4, kx=tuple(0.5 * m for m in range(1, 5)),
                     phase=c4_phases(0), **MAXWELLIAN)
+
+
+def keen(n: int = 1024, dt: float = 0.1, nsteps: int = 1000) -> Workload:
+    """KEEN waves (Section 4.3): f0 = f_M on [0, 2 pi / k) x [-6, 6), driven by
+    E_app with E_max = 0.2, k = 0.26, omega = 0.37, t_L = 69, t_R = 307,
+    t_wL = t_wR = 20."""
+    d = Drive()
+    return Workload(f"keen_{n}x{n}", n, n, 2.0 * math.pi / d.k, -6.0, 6.0, 17, dt, nsteps,
+                    "fp32_deltaf", amp=(), kx=(), phase=(), drive=d, **MAXWELLIAN)
 
 
 def landau_long() -> Workload:
