@@ -47,7 +47,8 @@ extern "C" {
 #define VOG_FP32_DELTAF  1  /* delta f = f - f_eq stored and advected in FP32 (Section 3.1) */
 #define VOG_FP64_DELTAF  2  /* delta f in FP64 */
 
-#define VOG_POISSON_FOURIER 0  /* Fourier solve, mode 0 set to zero (Section 3.2) */
+#define VOG_POISSON_FOURIER   0  /* Fourier solve, mode 0 set to zero (Section 3.2) */
+#define VOG_POISSON_TRAPEZOID 1  /* trapezoidal rule, with or without the zero-mean step (Section 3.2) */
 
 #define VOG_FIELD_SELF_CONSISTENT 0
 #define VOG_FIELD_ZERO            1  /* E held at zero: free streaming */
@@ -63,7 +64,7 @@ typedef struct vog_config {
     double vmin, vmax;   /* vmin < vmax */
     int degree;          /* odd Lagrange degree 2d+1, 1 <= degree <= min(17, nx-1, nv-1) */
     int precision;       /* VOG_FP64_PLAIN, VOG_FP32_DELTAF or VOG_FP64_DELTAF */
-    int poisson;         /* VOG_POISSON_FOURIER */
+    int poisson;         /* VOG_POISSON_FOURIER or VOG_POISSON_TRAPEZOID */
     int field;           /* VOG_FIELD_SELF_CONSISTENT or VOG_FIELD_ZERO */
     /* f_eq(v) = sum_g feq_a[g] exp(-(v - feq_c[g])^2 / (2 feq_sigma[g]^2)),
      * 1 <= n_feq <= 4, feq_sigma > 0.  It is the background of
@@ -74,6 +75,17 @@ typedef struct vog_config {
     /* L2 norm and total energy (Section 4.2) are computed every
      * moments_every steps (0: never). */
     int moments_every;
+    /* Trapezoidal solve only: 1 subtracts the mean of rho and of E (the
+     * zero-mean modification of Section 3.2); 0 uses rho - 1 and E as
+     * integrated from E_0 = 0. */
+    int zero_mean;
+    /* External drive of the KEEN-wave test (Section 4.3):
+     *   E_app(t, x) = drive_emax drive_k a(t) sin(drive_k x - drive_omega t),
+     *   a(t) = (0.5 (tanh((t - tl)/twl) - tanh((t - tr)/twr)) - eps) / (1 - eps),
+     * eps the same bracket at t0.  The v-advection uses E - E_app (the first
+     * half step at t^n, the second at t^{n+1}).  drive_emax = 0: no drive;
+     * otherwise twl, twr > 0 and drive_k, drive_omega finite. */
+    double drive_emax, drive_k, drive_omega, drive_t0, drive_tl, drive_tr, drive_twl, drive_twr;
 } vog_config;
 
 /* One record per time step, written on the device by the field solve. */
@@ -87,6 +99,7 @@ typedef struct vog_diag {
     double energy;     /* dx dv sum f v^2/2 + dx/2 sum E^2 (Section 4.2), or NaN */
     int32_t finite;    /* 1 if every E_i is finite */
     int32_t reserved;
+    double abs_rho_modes[7]; /* |rho_hat_m| for m = 1..7 (the mode history of Section 4.3) */
 } vog_diag;
 
 typedef struct vog_sim vog_sim;
@@ -133,11 +146,13 @@ int vog_get_f(vog_sim *sim, double *host_f);
  * host; elem_bytes receives 4 or 8.  host_buf holds nx*nv*elem_bytes bytes. */
 int vog_get_raw(vog_sim *sim, void *host_buf, size_t bytes, int *elem_bytes);
 
-/* Copies E at the current time level (nx FP64 values) to host. */
+/* Copies the self-consistent E at the current time level (nx FP64 values)
+ * to host. */
 int vog_get_E(vog_sim *sim, double *host_E);
 
-/* Replaces E (nx FP64 values) without touching f.  Used to drive a single
- * v-advection with a chosen field. */
+/* Replaces E (nx FP64 values) without touching f; the advecting field becomes
+ * E - E_app at the current time.  Used to drive a single v-advection with a
+ * chosen field. */
 int vog_set_E(vog_sim *sim, const double *host_E);
 
 /* Enqueues nsteps Strang steps of size dt (Section 1.1):
@@ -169,7 +184,8 @@ int vog_sweep(vog_sim *sim, int which, double arg);
  * ring capacity (4096 steps) are dropped. */
 int vog_get_diag(vog_sim *sim, vog_diag *out, int cap, int *n);
 
-/* Checkpoint: the stored array, E, step counter and time, bitwise. */
+/* Checkpoint: the stored array, E, the advecting field, step counter and
+ * time, bitwise. */
 size_t vog_state_bytes(const vog_sim *sim);
 int vog_get_state(vog_sim *sim, void *host_buf, size_t bytes);
 int vog_set_state(vog_sim *sim, const void *host_buf, size_t bytes);

@@ -265,8 +265,8 @@ __global__ __launch_bounds__(256) void sweep_kernel(const Batch b) {
     const double arg = b.a[blockIdx.y];
     double EA = 0.0, EB = 0.0, betaA, betaB;
     if constexpr (KIND == 0) {
-        EA = S.E[lineA];
-        EB = S.E[lineB];
+        EA = S.Eeff[lineA];
+        EB = S.Eeff[lineB];
         betaA = -arg * EA * S.inv_dv;
         betaB = -arg * EB * S.inv_dv;
     } else {
@@ -574,9 +574,13 @@ void launch_transpose(bool fp64, bool to_v, const Batch &b, int max_tiles, hipSt
 
 // ----------------------------------------------------------------- field solve
 
-// One block per sim, TPF = N/16 threads (N = nx).  rho_hat = FFT(rho); E_hat_m = rho_hat_m / (i k_m), with
-// E_hat_0 = E_hat_{N/2} = 0 (Section 3.2, Fourier variant); E = iFFT / N.
-// Writes the step's diagnostics record.
+// One block per sim, TPF = N/16 threads (N = nx).  rho_hat = FFT(rho) gives
+// the diagnostics (rho_hat_0 .. rho_hat_7) and, for the Fourier solve,
+// E_hat_m = rho_hat_m / (i k_m) with E_hat_0 = E_hat_{N/2} = 0 (Section 3.2),
+// E = iFFT.  The trapezoidal solve integrates rho - mean (zero_mean) or
+// rho - 1 from E_0 = 0 and, with zero_mean, subtracts the mean of E
+// (Section 3.2).  Writes E, the advecting field E - E_app(t) and the step's
+// diagnostics record.
 template <int N>
 constexpr int kFieldThreads = Fft<double, N>::TPF;
 
@@ -584,15 +588,32 @@ template <int N>
 __global__ __launch_bounds__(kFieldThreads<N>) void field_kernel(const Batch b) {
     using F = Fft<double, N>;
     constexpr int R = F::R, TPF = F::TPF;
+    constexpr int NW = (TPF + 63) / 64;  // waves in the block
+    constexpr int WL = TPF < 64 ? TPF : 64;
     __shared__ double lre[F::LDSN], lim[F::LDSN];
-    __shared__ double red[TPF];
-    __shared__ double rho01[3];
+    __shared__ double red[NW];
+    __shared__ double scan[TPF];
+    __shared__ double modes[8][2];
     __shared__ int bad[1];
 
     const SimDev &S = *b.s[blockIdx.x];
     const int t = threadIdx.x;
     const cx<double> *tab = (const cx<double> *)S.tw_x64;
     if (t == 0) bad[0] = 0;
+    if (t < 8) modes[t][0] = modes[t][1] = 0.0;
+
+    // block sum in a fixed order: xor-shuffles in each wave, then the waves
+    auto block_sum = [&](double x) {
+        for (int off = WL / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, WL);
+        if constexpr (NW > 1) {
+            __syncthreads();
+            if ((t & 63) == 0) red[t >> 6] = x;
+            __syncthreads();
+            x = red[0];
+            for (int wv = 1; wv < NW; ++wv) x += red[wv];
+        }
+        return x;
+    };
 
     cx<double> v[R];
     static_for<0, R>([&](auto rc) {
@@ -601,56 +622,106 @@ __global__ __launch_bounds__(kFieldThreads<N>) void field_kernel(const Batch b) 
     });
     F::template run<-1>(v, t, lre, lim, tab);
 
-    // rho_hat_0 and rho_hat_1 (unnormalised here).
+    // rho_hat_0 .. rho_hat_7 (unnormalised here).
     static_for<0, R>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         const int m = t + TPF * F::kpos(i);
-        if (m == 0) rho01[0] = v[i].re;
-        if (m == 1) {
-            rho01[1] = v[i].re;
-            rho01[2] = v[i].im;
+        if (m < 8) {
+            modes[m][0] = v[i].re;
+            modes[m][1] = v[i].im;
         }
     });
 
-    cx<double> Y[R];
-    const double twopi_L = 2.0 * M_PI / S.L;
-    static_for<0, R>([&](auto ic) {
-        constexpr int i = decltype(ic)::value;
-        constexpr int k = F::kpos(i);
-        const int m = t + TPF * k;
-        const int mt = 2 * m < N ? m : m - N;
-        if (m == 0 || 2 * m == N || S.field_zero) {
-            Y[k] = cx<double>{0.0, 0.0};
-        } else {
-            const double km = twopi_L * (double)mt;
-            Y[k] = cx<double>{v[i].im / km, -v[i].re / km};
+    double e[R];  // E at positions t + TPF kpos(i)
+    if (S.poisson == VOG_POISSON_TRAPEZOID) {
+        __syncthreads();  // modes visible
+        const double mean = S.zero_mean ? modes[0][0] / (double)N : 1.0;
+        // Contiguous chunk j = t R .. t R + R - 1 of rho~ = rho - mean and the
+        // increments dx (rho~_j + rho~_{j+1}) / 2 for j < N - 1.
+        double acc = 0.0, loc[R];
+        double rj = S.rho[t * R] - mean;
+        static_for<0, R>([&](auto jc) {
+            constexpr int jj = decltype(jc)::value;
+            const int j = t * R + jj;
+            loc[jj] = acc;  // sum of the chunk's increments before j
+            const double rn = (j + 1 < N) ? S.rho[j + 1] - mean : 0.0;
+            if (j + 1 < N) acc += S.dx * 0.5 * (rj + rn);
+            rj = rn;
+        });
+        scan[t] = acc;
+        __syncthreads();
+        if (t == 0) {
+            double run = 0.0;
+            for (int k = 0; k < TPF; ++k) {
+                const double c = scan[k];
+                scan[k] = run;
+                run += c;
+            }
         }
-    });
-    F::template run<1>(Y, t, lre, lim, tab);
+        __syncthreads();
+        const double off = scan[t];
+        double esum = 0.0;
+        static_for<0, R>([&](auto jc) {
+            constexpr int jj = decltype(jc)::value;
+            loc[jj] += off;
+            esum += loc[jj];
+        });
+        const double emean = S.zero_mean ? block_sum(esum) / (double)N : 0.0;
+        // back to the strided ownership used below: through LDS
+        __syncthreads();
+        static_for<0, R>([&](auto jc) {
+            constexpr int jj = decltype(jc)::value;
+            lre[F::pad(t * R + jj)] = loc[jj] - emean;
+        });
+        __syncthreads();
+        static_for<0, R>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            e[i] = lre[F::pad(t + TPF * F::kpos(i))];
+        });
+    } else {
+        // E_hat_m = rho_hat_m / (i k_m) = (Im rho_hat_m, -Re rho_hat_m) / k_m with
+        // the table invk[m] = 1 / (N k_m) (0 for m = 0, m = N/2, or a zero field;
+        // 1/N is the scale of the inverse transform).
+        cx<double> Y[R];
+        static_for<0, R>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            constexpr int k = F::kpos(i);
+            const double ik = S.invk[t + TPF * k];
+            Y[k] = cx<double>{v[i].im * ik, -v[i].re * ik};
+        });
+        F::template run<1>(Y, t, lre, lim, tab);
+        static_for<0, R>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            e[i] = Y[i].re;
+        });
+    }
 
     double e2 = 0.0;
-    const double invn = 1.0 / (double)N;
+    bool finite = true;
+    const double damp = b.drv_amp[blockIdx.x], dph = b.drv_ph[blockIdx.x];
     static_for<0, R>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         const int j = t + TPF * F::kpos(i);
-        const double e = Y[i].re * invn;
-        S.E[j] = e;
-        e2 += e * e;
-        if (!isfinite(e)) bad[0] = 1;
+        const double ej = S.field_zero ? 0.0 : e[i];
+        S.E[j] = ej;
+        S.Eeff[j] = damp == 0.0 ? ej : ej - damp * sin(S.drive_k * (j * S.dx) - dph);
+        e2 = fma(ej, ej, e2);
+        finite = finite && isfinite(ej);
     });
-    red[t] = e2;
-    __syncthreads();
-    for (int h = TPF / 2; h > 0; h >>= 1) {
-        if (t < h) red[t] += red[t + h];
-        __syncthreads();
-    }
+    if (!finite) bad[0] = 1;
+    e2 = block_sum(e2);
+    if constexpr (NW == 1) __syncthreads();  // modes and bad visible to thread 0
     if (t == 0) {
+        const double invn = 1.0 / (double)N;
         vog_diag d;
         d.step = b.step[blockIdx.x];
         d.t = b.t[blockIdx.x];
-        d.normE = sqrt(S.dx * red[0]);
-        d.rho0 = rho01[0] * invn;
-        d.abs_rho1 = sqrt(rho01[1] * rho01[1] + rho01[2] * rho01[2]) * invn;
+        d.normE = sqrt(S.dx * e2);
+        d.rho0 = modes[0][0] * invn;
+        d.abs_rho1 = sqrt(modes[1][0] * modes[1][0] + modes[1][1] * modes[1][1]) * invn;
+        for (int m = 1; m < 8; ++m)
+            d.abs_rho_modes[m - 1] =
+                m < N ? sqrt(modes[m][0] * modes[m][0] + modes[m][1] * modes[m][1]) * invn : 0.0;
         d.l2 = __builtin_nan("");
         d.energy = __builtin_nan("");
         d.finite = bad[0] ? 0 : 1;
@@ -678,29 +749,38 @@ LaunchFn field_launcher(int nx) {
 
 // ----------------------------------------------------------------- rho (v layout)
 
-// rho_i = dv sum_j f[i][j] + feq_const in FP64 with a fixed reduction order
-// (one block per x-column); used when the field is computed from a freshly set f.
+// rho_i = dv sum_j f[i][j] + feq_const, FP64 accumulation in a fixed order:
+// one wave per x-column i (4 per block), 16-byte loads, xor-shuffle reduction.
 template <typename T>
 __global__ __launch_bounds__(256) void rho_v_kernel(const Batch b) {
-    __shared__ double red[256];
     const SimDev &S = *b.s[blockIdx.y];
-    const int i = blockIdx.x;
-    if (i >= S.nx) return;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (i >= S.nx) return;  // wave-uniform; no block barrier follows
+    constexpr int VEC = 16 / sizeof(T);
     const T *row = (const T *)S.f + (size_t)i * S.nv;
     double acc = 0.0;
-    for (int j = threadIdx.x; j < S.nv; j += 256) acc += (double)row[j];
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-        __syncthreads();
+    if (S.nv % (64 * VEC) == 0) {
+        for (int j = lane * VEC; j < S.nv; j += 64 * VEC) {
+            if constexpr (sizeof(T) == 4) {
+                const float4 x = *reinterpret_cast<const float4 *>(row + j);
+                acc += ((double)x.x + (double)x.y) + ((double)x.z + (double)x.w);
+            } else {
+                const double2 x = *reinterpret_cast<const double2 *>(row + j);
+                acc += x.x + x.y;
+            }
+        }
+    } else {
+        for (int j = lane; j < S.nv; j += 64) acc += (double)row[j];
     }
-    if (threadIdx.x == 0) S.rho[i] = S.dv * red[0] + S.feq_const;
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) S.rho[i] = S.dv * acc + S.feq_const;
 }
 
 void launch_rho_v(bool fp64, const Batch &b, int max_nx, hipStream_t st) {
-    if (fp64) hipLaunchKernelGGL((rho_v_kernel<double>), dim3(max_nx, b.n), dim3(256), 0, st, b);
-    else hipLaunchKernelGGL((rho_v_kernel<float>), dim3(max_nx, b.n), dim3(256), 0, st, b);
+    const int blocks = (max_nx + 3) / 4;
+    if (fp64) hipLaunchKernelGGL((rho_v_kernel<double>), dim3(blocks, b.n), dim3(256), 0, st, b);
+    else hipLaunchKernelGGL((rho_v_kernel<float>), dim3(blocks, b.n), dim3(256), 0, st, b);
 }
 
 // ----------------------------------------------------------------- moments

@@ -71,7 +71,7 @@ void unit_roots(int n, std::vector<double> &re, std::vector<double> &im) {
 }
 
 struct Layout {
-    size_t f, g, E, part, rho, mom, tw_x, tw_v, eps_x, eps_v, tw_x64, feq_g, feq64, ring, dev, total;
+    size_t f, g, E, Eeff, part, rho, mom, tw_x, tw_v, eps_x, eps_v, tw_x64, invk, feq_g, feq64, ring, dev, total;
 };
 
 // How the x-sweep reaches the x-lines of the v-fastest array f[nx][nv]:
@@ -100,6 +100,7 @@ Layout layout_of(const vog_config &c) {
     L.f = take(cells * es);
     L.g = take(uses_fused_xsweep(c) ? 0 : cells * es);
     L.E = take(sizeof(double) * c.nx);
+    L.Eeff = take(sizeof(double) * c.nx);
     L.part = take(sizeof(double) * c.nx * (size_t)nparts);
     L.rho = take(sizeof(double) * c.nx);
     L.mom = take(sizeof(double) * 2 * c.nx);
@@ -108,6 +109,7 @@ Layout layout_of(const vog_config &c) {
     L.eps_x = take(2 * es * kEpsRow * (c.nx / fft_regs(c.nx)));
     L.eps_v = take(2 * es * kEpsRow * (c.nv / fft_regs(c.nv)));
     L.tw_x64 = take(2 * sizeof(double) * fft_tw_total(c.nx));
+    L.invk = take(sizeof(double) * c.nx);
     L.feq_g = take(es * VOG_MAX_FEQ * c.nv);
     L.feq64 = take(sizeof(double) * c.nv);
     L.ring = take(sizeof(vog_diag) * kRingCap);
@@ -164,7 +166,21 @@ int validate(const vog_config *c) {
     if (c->precision != VOG_FP64_PLAIN && c->precision != VOG_FP32_DELTAF &&
         c->precision != VOG_FP64_DELTAF)
         return fail(VOG_EINVAL, "unknown precision");
-    if (c->poisson != VOG_POISSON_FOURIER) return fail(VOG_EINVAL, "unknown Poisson solver");
+    if (c->poisson != VOG_POISSON_FOURIER && c->poisson != VOG_POISSON_TRAPEZOID)
+        return fail(VOG_EINVAL, "unknown Poisson solver");
+    if (c->zero_mean != 0 && c->zero_mean != 1) return fail(VOG_EINVAL, "zero_mean must be 0 or 1");
+    if (!isfinite(c->drive_emax)) return fail(VOG_EINVAL, "drive_emax must be finite");
+    if (c->drive_emax != 0.0) {
+        const double p[6] = {c->drive_k, c->drive_omega, c->drive_t0, c->drive_tl, c->drive_tr, 0.0};
+        for (int k = 0; k < 5; ++k)
+            if (!isfinite(p[k])) return fail(VOG_EINVAL, "drive parameters must be finite");
+        if (!(c->drive_twl > 0.0) || !(c->drive_twr > 0.0) || !isfinite(c->drive_twl) ||
+            !isfinite(c->drive_twr))
+            return fail(VOG_EINVAL, "drive widths must be finite and > 0");
+        const double eps = 0.5 * (tanh((c->drive_t0 - c->drive_tl) / c->drive_twl) -
+                                  tanh((c->drive_t0 - c->drive_tr) / c->drive_twr));
+        if (!(fabs(1.0 - eps) > 1e-12)) return fail(VOG_EINVAL, "drive envelope is already on at t0");
+    }
     if (c->field != VOG_FIELD_SELF_CONSISTENT && c->field != VOG_FIELD_ZERO)
         return fail(VOG_EINVAL, "unknown field mode");
     if (c->n_feq < 1 || c->n_feq > VOG_MAX_FEQ) return fail(VOG_EINVAL, "n_feq must be in [1, 4]");
@@ -175,6 +191,20 @@ int validate(const vog_config *c) {
     }
     if (c->moments_every < 0) return fail(VOG_EINVAL, "moments_every must be >= 0");
     return VOG_OK;
+}
+
+// Drive of Section 4.3: emax k a(t) and the phase omega t at time t.
+void drive_at(const vog_config &c, double t, double *amp, double *phase) {
+    if (c.drive_emax == 0.0) {
+        *amp = 0.0;
+        *phase = 0.0;
+        return;
+    }
+    const double eps = 0.5 * (tanh((c.drive_t0 - c.drive_tl) / c.drive_twl) -
+                              tanh((c.drive_t0 - c.drive_tr) / c.drive_twr));
+    const double br = 0.5 * (tanh((t - c.drive_tl) / c.drive_twl) - tanh((t - c.drive_tr) / c.drive_twr));
+    *amp = c.drive_emax * c.drive_k * (br - eps) / (1.0 - eps);
+    *phase = c.drive_omega * t;
 }
 
 double feq_at(const vog_config &c, double v) {
@@ -393,6 +423,7 @@ int run_field(vog_sim *lead, const std::vector<vog_sim *> &sims, const std::vect
                 b.s[k] = sims[i]->dev;
                 b.step[k] = stepno[i];
                 b.t[k] = tnow[i];
+                drive_at(sims[i]->cfg, tnow[i], &b.drv_amp[k], &b.drv_ph[k]);
             }
             EventPair *p;
             prof_begin(lead, K_FIELD, &p);
@@ -540,6 +571,7 @@ void vog_config_default(vog_config *c) {
     c->feq_c[0] = 0.0;
     c->feq_sigma[0] = 1.0;
     c->moments_every = 0;
+    c->zero_mean = 1;
 }
 
 int vog_config_validate(const vog_config *c) { return validate(c); }
@@ -602,6 +634,7 @@ int vog_create(const vog_config *c, void *dev_workspace, size_t bytes, void *hip
     D.f = s->ws + L.f;
     D.g = s->fused ? nullptr : s->ws + L.g;
     D.E = (double *)(s->ws + L.E);
+    D.Eeff = (double *)(s->ws + L.Eeff);
     D.part = (double *)(s->ws + L.part);
     D.rho = (double *)(s->ws + L.rho);
     D.mom = (double *)(s->ws + L.mom);
@@ -610,6 +643,7 @@ int vog_create(const vog_config *c, void *dev_workspace, size_t bytes, void *hip
     D.eps_x = s->ws + L.eps_x;
     D.eps_v = s->ws + L.eps_v;
     D.tw_x64 = (const double *)(s->ws + L.tw_x64);
+    D.invk = (const double *)(s->ws + L.invk);
     D.feq_g = s->ws + L.feq_g;
     D.feq64 = (const double *)(s->ws + L.feq64);
     D.ring = (vog_diag *)(s->ws + L.ring);
@@ -620,6 +654,9 @@ int vog_create(const vog_config *c, void *dev_workspace, size_t bytes, void *hip
     D.field_zero = c->field == VOG_FIELD_ZERO;
     D.n_feq = c->n_feq;
     D.nparts = (nv + kTile - 1) / kTile;
+    D.poisson = c->poisson;
+    D.zero_mean = c->zero_mean;
+    D.drive_k = c->drive_emax != 0.0 ? c->drive_k : 0.0;
     D.fp64 = fp64;
     D.L = c->L;
     D.vmin = c->vmin;
@@ -679,6 +716,16 @@ int vog_create(const vog_config *c, void *dev_workspace, size_t bytes, void *hip
         if ((rc = upload_vec(s->ws + L.feq_g, fg32, s->stream)) != VOG_OK) return bail(rc);
     }
     if ((rc = upload_vec(s->ws + L.tw_x64, tw64x, s->stream)) != VOG_OK) return bail(rc);
+    // 1 / (nx k_m) for the Fourier field solve: k_m = 2 pi mt / L with mt the
+    // signed mode index; modes 0 and nx/2 (and every mode for a zero field) get 0.
+    std::vector<double> invk(nx, 0.0);
+    if (c->field == VOG_FIELD_SELF_CONSISTENT)
+        for (int m = 1; m < nx; ++m) {
+            if (2 * m == nx) continue;
+            const int mt = 2 * m < nx ? m : m - nx;
+            invk[m] = 1.0 / ((double)nx * (2.0 * M_PI * (double)mt / c->L));
+        }
+    if ((rc = upload_vec(s->ws + L.invk, invk, s->stream)) != VOG_OK) return bail(rc);
     if ((rc = upload_vec(s->ws + L.feq64, s->feq64, s->stream)) != VOG_OK) return bail(rc);
     if ((rc = upload(s->ws + L.dev, &D, sizeof(D), s->stream)) != VOG_OK) return bail(rc);
     // The staging vectors above are temporaries: wait until the copies are done.
@@ -774,7 +821,14 @@ int vog_set_E(vog_sim *s, const double *host_E) {
     if (!s || !host_E) return fail(VOG_EINVAL, "NULL argument");
     int rc = device_guard(s);
     if (rc != VOG_OK) return rc;
-    HIP_TRY(hipMemcpyAsync(s->host_dev.E, host_E, sizeof(double) * s->cfg.nx, hipMemcpyHostToDevice, s->stream));
+    const int nx = s->cfg.nx;
+    std::vector<double> eff(host_E, host_E + nx);
+    double amp, ph;
+    drive_at(s->cfg, s->t, &amp, &ph);
+    if (amp != 0.0)
+        for (int i = 0; i < nx; ++i) eff[i] -= amp * sin(s->cfg.drive_k * (i * s->host_dev.dx) - ph);
+    HIP_TRY(hipMemcpyAsync(s->host_dev.E, host_E, sizeof(double) * nx, hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipMemcpyAsync(s->host_dev.Eeff, eff.data(), sizeof(double) * nx, hipMemcpyHostToDevice, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
     return VOG_OK;
 }
@@ -839,7 +893,7 @@ int vog_get_diag(vog_sim *s, vog_diag *out, int cap, int *n) {
 size_t vog_state_bytes(const vog_sim *s) {
     if (!s) return 0;
     const size_t es = s->fp64 ? 8 : 4;
-    return 16 + (size_t)s->cfg.nx * s->cfg.nv * es + sizeof(double) * s->cfg.nx;
+    return 16 + (size_t)s->cfg.nx * s->cfg.nv * es + 2 * sizeof(double) * s->cfg.nx;
 }
 
 int vog_get_state(vog_sim *s, void *host_buf, size_t bytes) {
@@ -853,6 +907,8 @@ int vog_get_state(vog_sim *s, void *host_buf, size_t bytes) {
     memcpy(p + 8, &s->t, 8);
     HIP_TRY(hipMemcpyAsync(p + 16, s->host_dev.f, fb, hipMemcpyDeviceToHost, s->stream));
     HIP_TRY(hipMemcpyAsync(p + 16 + fb, s->host_dev.E, sizeof(double) * s->cfg.nx, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipMemcpyAsync(p + 16 + fb + sizeof(double) * s->cfg.nx, s->host_dev.Eeff,
+                           sizeof(double) * s->cfg.nx, hipMemcpyDeviceToHost, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
     return VOG_OK;
 }
@@ -871,6 +927,8 @@ int vog_set_state(vog_sim *s, const void *host_buf, size_t bytes) {
     if (st < 0 || !isfinite(tt)) return fail(VOG_EINVAL, "corrupt state header");
     HIP_TRY(hipMemcpyAsync(s->host_dev.f, p + 16, fb, hipMemcpyHostToDevice, s->stream));
     HIP_TRY(hipMemcpyAsync(s->host_dev.E, p + 16 + fb, sizeof(double) * s->cfg.nx, hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipMemcpyAsync(s->host_dev.Eeff, p + 16 + fb + sizeof(double) * s->cfg.nx,
+                           sizeof(double) * s->cfg.nx, hipMemcpyHostToDevice, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
     s->step = st;
     s->t = tt;

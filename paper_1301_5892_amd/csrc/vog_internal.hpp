@@ -19,7 +19,8 @@ constexpr int kTile = 64;                // transpose tile edge
 struct SimDev {
     void *f;            // [nx][nv]  f or delta f, storage precision (v fastest)
     void *g;            // [nv][nx]  transposed copy used by the x-sweep
-    double *E;          // [nx]      field at the current time level
+    double *E;          // [nx]      self-consistent field at the current time level
+    double *Eeff;       // [nx]      advecting field E - E_app at the current time level
     double *part;       // [nparts][nx] partial velocity sums, one row per 64 velocities
     double *rho;        // [nx]      charge density rho_i = int f dv
     double *mom;        // [nx][2]   per-line moment sums
@@ -28,10 +29,12 @@ struct SimDev {
     const void *eps_x;  // [nx / 16][10] exp(2 pi i t q / nx), symbol table for the x-sweep
     const void *eps_v;  // [nv / 16][10] exp(2 pi i t q / nv)
     const double *tw_x64;  // FP64 twiddle rows for length nx (field solve)
+    const double *invk;    // [nx] 1 / (nx k_m), k_m = 2 pi mt / L; 0 at m = 0, nx/2 (field solve)
     const void *feq_g;  // [n_feq][nv] component values f_g(v_j), storage precision
     const double *feq64;    // [nv] f_eq(v_j), FP64
     vog_diag *ring;     // [kRingCap]
-    int nx, nv, d, deltaf, field_zero, n_feq, nparts, fp64;
+    int nx, nv, d, deltaf, field_zero, n_feq, nparts, fp64, poisson, zero_mean;
+    double drive_k;     // wavenumber of the external drive (0: none)
     double L, vmin, dx, dv, inv_dx, inv_dv;
     double feq_c[VOG_MAX_FEQ], feq_inv_s2[VOG_MAX_FEQ];
     double feq_const;   // dv * sum_j f_eq(v_j) (delta f), else 0
@@ -46,6 +49,8 @@ struct Batch {
     double a[kMaxBatch];      // tau (v-sweep), dt (x-sweep)
     double t[kMaxBatch];      // time after the step (field solve)
     int64_t step[kMaxBatch];  // step number after the step (field solve)
+    double drv_amp[kMaxBatch];  // emax k a(t) of the drive at t (field solve)
+    double drv_ph[kMaxBatch];   // omega t (field solve)
 };
 
 enum Kind { K_SWEEP_V = 0, K_SWEEP_X = 1, K_T_VX = 2, K_T_XV = 3, K_FIELD = 4, K_MOMENTS = 5, K_RHO = 6 };

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libvog.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, EBUSY = 0, -1, -2, -3, -4, -5
 FP64_PLAIN, FP32_DELTAF, FP64_DELTAF = 0, 1, 2
-POISSON_FOURIER = 0
+POISSON_FOURIER, POISSON_TRAPEZOID = 0, 1
 FIELD_SELF_CONSISTENT, FIELD_ZERO = 0, 1
 MAX_FEQ = 4
 NUM_KINDS = 7
@@ -41,19 +41,25 @@ class Config(ctypes.Structure):
                 ("n_feq", ctypes.c_int),
                 ("feq_a", ctypes.c_double * MAX_FEQ), ("feq_c", ctypes.c_double * MAX_FEQ),
                 ("feq_sigma", ctypes.c_double * MAX_FEQ),
-                ("moments_every", ctypes.c_int)]
+                ("moments_every", ctypes.c_int), ("zero_mean", ctypes.c_int),
+                ("drive_emax", ctypes.c_double), ("drive_k", ctypes.c_double),
+                ("drive_omega", ctypes.c_double), ("drive_t0", ctypes.c_double),
+                ("drive_tl", ctypes.c_double), ("drive_tr", ctypes.c_double),
+                ("drive_twl", ctypes.c_double), ("drive_twr", ctypes.c_double)]
 
 
 class Diag(ctypes.Structure):
     _fields_ = [("step", ctypes.c_int64), ("t", ctypes.c_double), ("normE", ctypes.c_double),
                 ("rho0", ctypes.c_double), ("abs_rho1", ctypes.c_double),
                 ("l2", ctypes.c_double), ("energy", ctypes.c_double),
-                ("finite", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("finite", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("abs_rho_modes", ctypes.c_double * 7)]
 
 
 DIAG_DTYPE = np.dtype([("step", np.int64), ("t", np.float64), ("normE", np.float64),
                        ("rho0", np.float64), ("abs_rho1", np.float64), ("l2", np.float64),
-                       ("energy", np.float64), ("finite", np.int32), ("reserved", np.int32)])
+                       ("energy", np.float64), ("finite", np.int32), ("reserved", np.int32),
+                       ("abs_rho_modes", np.float64, (7,))])
 assert DIAG_DTYPE.itemsize == ctypes.sizeof(Diag)
 
 EXPORTS = ["vog_config_default", "vog_config_validate", "vog_workspace_bytes", "vog_create",
@@ -134,8 +140,14 @@ def make_config(w, moments_every: int = 0, precision: Optional[str] = None) -> C
     c.L, c.vmin, c.vmax = w.L, w.vmin, w.vmax
     c.degree = w.degree
     c.precision = PRECISION[precision or w.precision]
-    c.poisson = POISSON_FOURIER
+    c.poisson = POISSON_TRAPEZOID if w.poisson == "trapezoid" else POISSON_FOURIER
+    c.zero_mean = int(bool(w.zero_mean))
     c.field = FIELD_ZERO if w.field == "zero" else FIELD_SELF_CONSISTENT
+    if w.drive is not None:
+        d = w.drive
+        c.drive_emax, c.drive_k, c.drive_omega = d.emax, d.k, d.omega
+        c.drive_t0, c.drive_tl, c.drive_tr = d.t0, d.tl, d.tr
+        c.drive_twl, c.drive_twr = d.twl, d.twr
     c.n_feq = len(w.feq_a)
     for g in range(c.n_feq):
         c.feq_a[g], c.feq_c[g], c.feq_sigma[g] = w.feq_a[g], w.feq_c[g], w.feq_sigma[g]

@@ -25,6 +25,14 @@ def rel(a, b):
     return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
 
 
+def rel_field(E, o):
+    """E error relative to (L / 2 pi) max|rho|, the field a unit relative
+    error of rho produces: E comes from rho - mean(rho), so when |E| is far
+    below that scale the rounding of rho dominates its relative error."""
+    scale = max(np.max(np.abs(o.E)), o.w.L / (2 * math.pi) * np.max(np.abs(o.rho)))
+    return float(np.max(np.abs(np.asarray(E) - o.E)) / scale)
+
+
 def sim_of(gpu, w, **kw):
     return gpu.Sim(w, **kw)
 
@@ -340,3 +348,69 @@ def test_step_rejects_bad_dt(gpu):
         s.step(1, dt=float("nan"))
     with pytest.raises(gpu.VogError):
         s.step(1, dt=-0.1)
+
+
+# ---------------------------------------------------------------- variants
+
+@pytest.mark.parametrize("zero_mean", [True, False])
+@pytest.mark.parametrize("nx,nv", [(64, 128), (256, 64), (4096, 16), (16, 32)])
+def test_trapezoid_field(gpu, nx, nv, zero_mean):
+    deg = min(17, min(nx, nv) - 1)
+    w = workloads.landau_weak().replace(nx=nx, nv=nv, degree=deg, poisson="trapezoid",
+                                         zero_mean=zero_mean, amp=(0.1, 0.02), kx=(0.5, 2.0),
+                                         phase=(0.0, 0.7))
+    s = sim_of(gpu, w).init()
+    o = oracle.Oracle(w).init()
+    assert rel(s.get_E(), o.E) < TOL64
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64_plain", TOL64), ("fp32_deltaf", TOL32)])
+def test_trapezoid_steps(gpu, precision, tol):
+    w = workloads.landau_strong().replace(precision=precision, poisson="trapezoid",
+                                           zero_mean=precision != "fp64_plain")
+    s = sim_of(gpu, w).init()
+    o = oracle.Oracle(w).init()
+    s.step(10)
+    o.step(10)
+    got = s.get_raw() if precision == "fp32_deltaf" else s.get_f()
+    assert rel(got, o.f) < tol
+    assert rel(s.get_E(), o.E) < max(tol, 1e-11)
+
+
+@pytest.mark.parametrize("n,precision,tol,nsteps", [(64, "fp64_plain", TOL64, 30),
+                                                    (256, "fp32_deltaf", TOL32, 10),
+                                                    (1024, "fp32_deltaf", TOL32, 3)])
+def test_keen_driven(gpu, n, precision, tol, nsteps):
+    # Start inside the drive ramp (t0 shifted so that E_app is already large).
+    d = workloads.Drive(t0=-60.0)
+    w = workloads.keen(n, 0.1, nsteps).replace(precision=precision, drive=d)
+    s = sim_of(gpu, w).init()
+    o = oracle.Oracle(w).init()
+    s.step(nsteps)
+    od = o.step(nsteps)
+    got = s.get_raw() if precision == "fp32_deltaf" else s.get_f()
+    assert rel(got, o.f) < tol
+    if precision == "fp32_deltaf":
+        assert rel(s.get_E(), o.E) < tol
+    else:
+        assert rel_field(s.get_E(), o) < tol
+    dg = s.diag()
+    assert np.max(np.abs(dg["normE"][1:] - od[:, 0]) / od[:, 0]) < max(tol, 1e-9)
+    modes = o.rho_modes(7)
+    # |rho_hat_m|, m = 1..7, compared at the parity tolerance relative to the largest mode
+    assert np.max(np.abs(dg["abs_rho_modes"][-1] - modes)) < max(tol, 1e-9) * np.max(modes)
+
+
+def test_drive_checkpoint_bitwise(gpu):
+    d = workloads.Drive(t0=-60.0)
+    w = workloads.keen(256, 0.1, 10)
+    w = w.replace(drive=d)
+    a = sim_of(gpu, w).init()
+    a.step(9)
+    ref = a.get_raw().copy()
+    b = sim_of(gpu, w).init()
+    b.step(4)
+    c = sim_of(gpu, w)
+    c.set_state(b.get_state())
+    c.step(5)
+    assert np.array_equal(c.get_raw(), ref)
