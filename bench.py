@@ -2,15 +2,23 @@
 
 Default workload: the 4096 x 4096 large-grid case (FP32 delta f, degree 17,
 dt = 0.02), the configuration the metric is quoted on.  One "step" is one
-full Strang step (v-sweep, transpose, x-sweep, transpose + rho, field solve,
-v-sweep).  The timed region holds exactly --steps steps, bracketed by device
-synchronisation.  A second pass of the same number of steps records HIP events
-on the sim's stream around every kernel launch; they give each kernel's
-average duration for the roofline.
+full Strang step: v-sweep (dt/2), x-sweep (dt) on the v-fastest layout with
+the velocity row sums of rho, FP64 field solve, v-sweep (dt/2).  The timed
+region holds exactly --steps steps, bracketed by device synchronisation.  A
+second pass of the same number of steps records HIP events on the sim's
+stream around every kernel launch; they give each kernel's average duration
+for the roofline.
 
 Prints one JSON line with the headline FP32 delta-f rate, the FP64 plain
-rate on the same GPU, the roofline of the dominant kernel, the CPU-oracle
-baseline and (unless --no-serving) the serving-mix latency summary.
+rate on the same GPU, the roofline of the dominant kernel (with the HBM bytes
+rocprofv3 counted, when the committed measurement matches the current kernel
+sources), the achievable device-copy bandwidth, a batch of 16 large-grid sims
+(1 GiB of f, larger than the 256 MB Infinity Cache), the CPU-oracle baseline
+and (unless --no-serving) the serving-mix latency summary.
+
+`--summarize-rocprof DIR` instead turns the CSV output of the three rocprofv3
+runs listed in PROFILE_COMMANDS into the text summaries under profiles/ and
+the per-launch HBM traffic table profiles/traffic.json.
 """
 from __future__ import annotations
 
@@ -44,6 +52,12 @@ def parse():
     p.add_argument("--copy-calibration", action="store_true",
                    help="run one plain 256 MiB device-to-device copy first (a known-size "
                         "kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
+    p.add_argument("--dram-sims", type=int, default=16,
+                   help="sims of the workload stepped together through vog_step_batch "
+                        "(16 large-grid FP32 sims hold 1 GiB of f); 0 skips this leg")
+    p.add_argument("--summarize-rocprof", metavar="DIR", default=None,
+                   help="write profiles/ summaries from the rocprofv3 CSV output under DIR "
+                        "(subfolders kt/, fetch/, write/ and kt.log, as in PROFILE_COMMANDS)")
     return p.parse_args()
 
 
@@ -68,6 +82,51 @@ def stored_traffic(kind: str, workload: str, precision: str):
     if not e or e.get("kernel_source_hash") != kernel_source_hash():
         return None
     return e.get("bytes_per_launch")
+
+
+def run_dram(w, nsims, steps, warmup):
+    """nsims independent FP32 delta-f sims of the workload advanced together
+    by vog_step_batch: a working set several times the Infinity Cache, so
+    the rate has to hold from HBM."""
+    import torch
+    from paper_1301_5892_amd import vog
+
+    sims = [vog.Sim(w, precision="fp32_deltaf").init() for _ in range(nsims)]
+    vog.step_batch(sims, warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    vog.step_batch(sims, steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    finite = True
+    for sm in sims:
+        d = sm.diag()
+        finite = finite and bool(d.size == 0 or d["finite"][-1] == 1)
+    out = {"sims": nsims, "f_bytes": nsims * w.cells * 4, "steps": steps,
+           "value": nsims * w.cells * steps / el, "unit": "cell-updates/s",
+           "ms_per_step": el / steps * 1e3, "finite": finite}
+    out["algorithmic_gbs"] = out["value"] * 24 / 1e9
+    for sm in sims:
+        sm.close()
+    return out
+
+
+def copy_bandwidth(nbytes=1 << 30, reps=20):
+    """Achievable HBM bandwidth: a plain device-to-device copy of nbytes
+    (read + write counted), best of reps."""
+    import torch
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t0)
+    del src, dst
+    return 2 * nbytes / best / 1e9
 
 
 def run_gpu(w, precision, steps, warmup):
@@ -148,8 +207,185 @@ def cpu_baseline(w, seconds):
                       f"{steps} Strang steps from f0 ({el:.1f} s)"}
 
 
+# ---------------------------------------------------------------- rocprofv3 summaries
+# The three profiling runs the committed summaries come from, run from /tmp
+# with TMPDIR=/tmp ({out}: output folder, {root}: repository root).  The
+# kernel trace times the same bench command as the headline (fewer steps, the
+# batched leg off so that every launch of a kernel has the workload's shape);
+# the two counter runs add one 256 MiB device copy as the known-size kernel
+# that scales FETCH_SIZE and WRITE_SIZE to bytes.
+PROFILE_COMMANDS = {
+    "kt": "rocprofv3 --kernel-trace --stats -f csv -d {out}/kt -o kt -- python3 {root}/bench.py "
+          "--steps 100 --warmup 10 --no-serving --no-cpu-baseline --dram-sims 0 > {out}/kt.log",
+    "fetch": "rocprofv3 --pmc FETCH_SIZE -f csv -d {out}/fetch -o fetch -- python3 {root}/bench.py "
+             "--steps 2 --warmup 1 --no-serving --no-cpu-baseline --dram-sims 0 --copy-calibration",
+    "write": "rocprofv3 --pmc WRITE_SIZE -f csv -d {out}/write -o write -- python3 {root}/bench.py "
+             "--steps 2 --warmup 1 --no-serving --no-cpu-baseline --dram-sims 0 --copy-calibration",
+}
+COPY_CALIBRATION_BYTES = 256 << 20
+
+
+def classify_kernel(name):
+    """(kind, precision) of a libvog kernel name as the bench labels them;
+    ("copy", None) for the runtime's copy kernel; None for anything else."""
+    if "copyBuffer" in name:
+        return ("copy", None)
+    if "vog::" not in name:
+        return None
+    prec = "fp32_deltaf" if "<float" in name else ("fp64_plain" if "<double" in name else None)
+    if "xsweep_fused_kernel" in name:
+        return ("sweep_x", prec)
+    if "sweep_kernel" in name:
+        return ("sweep_x" if name.split("(")[0].rstrip().endswith(", 1>") else "sweep_v", prec)
+    if "transpose_kernel" in name:
+        return ("transpose", prec)
+    if "rho_v_kernel" in name or "rho_reduce_kernel" in name:
+        return ("rho_reduce", prec)
+    if "field_kernel" in name:
+        return ("field", "fp64")
+    if "moments" in name:
+        return ("moments", prec)
+    return None
+
+
+def _csv_rows(folder, suffix):
+    import csv
+    import glob
+    paths = sorted(glob.glob(os.path.join(folder, "**", "*" + suffix), recursive=True))
+    if not paths:
+        raise SystemExit(f"no *{suffix} under {folder}")
+    rows = []
+    for pth in paths:
+        with open(pth, newline="") as fh:
+            rows.extend({k.strip().lower(): v for k, v in r.items()} for r in csv.DictReader(fh))
+    return rows
+
+
+def _counter_per_kernel(folder):
+    """kernel name -> list of per-dispatch counter values (KiB)."""
+    out = {}
+    for r in _csv_rows(folder, "counter_collection.csv"):
+        out.setdefault(r["kernel_name"], []).append(float(r["counter_value"]))
+    return out
+
+
+def _last_json(path):
+    if not os.path.exists(path):
+        return None
+    rec = None
+    with open(path) as fh:
+        for line in fh:
+            line = line.strip()
+            if line.startswith("{"):
+                try:
+                    rec = json.loads(line)
+                except ValueError:
+                    pass
+    return rec
+
+
+def summarize_rocprof(folder, wname):
+    """Write profiles/kernel_trace_<workload>.md, profiles/hbm_traffic_<workload>.md
+    and profiles/traffic.json from the output of PROFILE_COMMANDS."""
+    prof_dir = os.path.join(ROOT, "profiles")
+    os.makedirs(prof_dir, exist_ok=True)
+    cmds = {k: v.format(out="/root/repo/gpurun_out/prof", root="/root/repo")
+            for k, v in PROFILE_COMMANDS.items()}
+    bench_rec = _last_json(os.path.join(folder, "kt.log"))
+
+    # kernel trace statistics
+    stats = _csv_rows(os.path.join(folder, "kt"), "kernel_stats.csv")
+    lines = [f"# Kernel trace, {wname}", "",
+             "Command (from /tmp, TMPDIR=/tmp):", "", "```", cmds["kt"], "```", "",
+             "| kernel | kind | precision | calls | avg us | min us | max us | % time |",
+             "|---|---|---|---|---|---|---|---|"]
+    trace_avg = {}
+    for r in sorted(stats, key=lambda r: -float(r.get("totaldurationns", 0))):
+        name = r["name"]
+        c = classify_kernel(name)
+        if c is None:
+            continue
+        avg = float(r["averagens"]) / 1e3
+        if c[0] != "copy":
+            trace_avg[c] = avg
+        lines.append(f"| `{name.split('(')[0]}` | {c[0]} | {c[1] or '-'} | {r['calls']} | "
+                     f"{avg:.2f} | {float(r['minns']) / 1e3:.2f} | {float(r['maxns']) / 1e3:.2f} | "
+                     f"{float(r['percentage']):.1f} |")
+    if bench_rec:
+        lines += ["", "HIP-event averages the bench printed in the same run (ms per launch):", ""]
+        for label, rf in (("fp32_deltaf", bench_rec.get("roofline")),
+                          ("fp64_plain", (bench_rec.get("fp64_plain") or {}).get("roofline"))):
+            if rf:
+                tr = trace_avg.get((rf["kernel"], label))
+                lines.append(f"- {label} {rf['kernel']}: events {rf['avg_launch_ms'] * 1e3:.2f} us, "
+                             f"trace {tr:.2f} us" if tr else
+                             f"- {label} {rf['kernel']}: events {rf['avg_launch_ms'] * 1e3:.2f} us")
+        lines.append(f"- headline ms/step (no events): {bench_rec['ms_per_step']:.4f}")
+    with open(os.path.join(prof_dir, f"kernel_trace_{wname}.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+    # HBM traffic from FETCH_SIZE / WRITE_SIZE, scaled by the copy kernel
+    fetch = _counter_per_kernel(os.path.join(folder, "fetch"))
+    write = _counter_per_kernel(os.path.join(folder, "write"))
+    cal_kib = COPY_CALIBRATION_BYTES / 1024.0
+    copy_f = max((max(v) for k, v in fetch.items() if "copyBuffer" in k), default=None)
+    copy_w = max((max(v) for k, v in write.items() if "copyBuffer" in k), default=None)
+    if not copy_f or not copy_w:
+        raise SystemExit("no copy kernel in the counter output")
+    kf, kw = cal_kib / copy_f, cal_kib / copy_w
+    src_hash = kernel_source_hash()
+    table_path = os.path.join(prof_dir, "traffic.json")
+    table = {}
+    if os.path.exists(table_path):
+        with open(table_path) as fh:
+            table = json.load(fh)
+    lines = [f"# HBM traffic per launch, {wname}", "",
+             "Commands (from /tmp, TMPDIR=/tmp):", "", "```", cmds["fetch"], cmds["write"], "```", "",
+             f"Calibration: one {COPY_CALIBRATION_BYTES >> 20} MiB device-to-device copy "
+             f"(`__amd_rocclr_copyBuffer`) reads FETCH_SIZE = {copy_f:.0f} KiB and "
+             f"WRITE_SIZE = {copy_w:.0f} KiB against {cal_kib:.0f} KiB moved each way, so the "
+             f"counters are scaled by {kf:.4f} (fetch) and {kw:.4f} (write).  FETCH_SIZE counts "
+             f"L2 misses sent to the fabric, so Infinity Cache hits are included.", "",
+             f"Kernel sources hash: `{src_hash}`", "",
+             "| kernel | kind | precision | dispatches | FETCH KiB | WRITE KiB | scaled MB read | "
+             "scaled MB written | algorithmic MB |", "|---|---|---|---|---|---|---|---|---|"]
+    es = {"fp32_deltaf": 4, "fp64_plain": 8}
+    import workloads
+    wl = {x.name: x for x in workloads.all_named()}.get(wname)
+    for name in sorted(set(fetch) & set(write)):
+        c = classify_kernel(name)
+        if c is None or c[0] == "copy":
+            continue
+        f_avg = sum(fetch[name]) / len(fetch[name])
+        w_avg = sum(write[name]) / len(write[name])
+        rd, wr = f_avg * 1024 * kf, w_avg * 1024 * kw
+        alg = None
+        if wl and c[1] in es:
+            # a sweep reads and writes f once; the velocity sums read it once
+            alg = {"sweep_v": 2, "sweep_x": 2, "rho_reduce": 1}.get(c[0], 0) * es[c[1]] * wl.cells
+            alg = alg or None
+        lines.append(f"| `{name.split('(')[0]}` | {c[0]} | {c[1] or '-'} | {len(fetch[name])} | "
+                     f"{f_avg:.0f} | {w_avg:.0f} | {rd / 1e6:.2f} | {wr / 1e6:.2f} | "
+                     f"{'-' if alg is None else f'{alg / 1e6:.2f}'} |")
+        if c[1] in es:
+            table[f"{c[0]}/{wname}/{c[1]}"] = {
+                "kernel": name.split("(")[0], "kernel_source_hash": src_hash,
+                "fetch_bytes": rd, "write_bytes": wr, "bytes_per_launch": rd + wr,
+                "fetch_scale": kf, "write_scale": kw}
+    with open(os.path.join(prof_dir, f"hbm_traffic_{wname}.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    with open(table_path, "w") as fh:
+        json.dump(table, fh, indent=1, sort_keys=True)
+    print(f"wrote profiles/kernel_trace_{wname}.md, profiles/hbm_traffic_{wname}.md, "
+          f"profiles/traffic.json")
+
+
 def main():
     args = parse()
+    if args.summarize_rocprof:
+        import workloads
+        summarize_rocprof(args.summarize_rocprof, getattr(workloads, args.workload)().name)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); "
               f"independent simulations shard one per GPU, see DESIGN.md", file=sys.stderr)
@@ -197,6 +433,9 @@ def main():
                           "note": "Table 1, N = 4096, FP32 delta f, KEEN workload; context only"},
         "build": vog.build_info(),
     }
+    if not args.copy_calibration:
+        # (counter runs keep the calibration copy the only large copy kernel)
+        out["roofline"]["achievable_copy_gbs"] = copy_bandwidth()
     if not args.no_fp64:
         el64, prof64, fin64, el64p = run_gpu(w, "fp64_plain", K, W)
         out["fp64_plain"] = {"value": w.cells * K / el64, "ms_per_step": el64 / K * 1e3,
@@ -205,6 +444,8 @@ def main():
                              "kernels_ms_per_step": {k: v[0] / K for k, v in prof64.items()},
                              "roofline": roofline_for(w, "fp64_plain", prof64, K)}
         out["fp32_over_fp64"] = out["value"] / out["fp64_plain"]["value"]
+    if args.dram_sims > 0:
+        out["dram_batch"] = run_dram(w, args.dram_sims, K, W)
     if not args.no_serving:
         try:
             from paper_1301_5892_amd import serving
