@@ -49,7 +49,8 @@ class _Cfg(ctypes.Structure):
                 ("drive_emax", ctypes.c_double), ("drive_k", ctypes.c_double),
                 ("drive_omega", ctypes.c_double), ("drive_t0", ctypes.c_double),
                 ("drive_tl", ctypes.c_double), ("drive_tr", ctypes.c_double),
-                ("drive_twl", ctypes.c_double), ("drive_twr", ctypes.c_double)]
+                ("drive_twl", ctypes.c_double), ("drive_twr", ctypes.c_double),
+                ("interp", ctypes.c_int), ("merge_v", ctypes.c_int)]
 
 
 _lib = None
@@ -67,6 +68,9 @@ def lib():
         L.orc_split_shift.argtypes = [ctypes.c_double, ctypes.POINTER(ctypes.c_long), _D]
         L.orc_circulant_row.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _D]
         L.orc_advect_line.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _D, _D]
+        L.orc_bspline.argtypes = [ctypes.c_int, ctypes.c_double]
+        L.orc_bspline.restype = ctypes.c_double
+        L.orc_advect_line_bspline.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _D, _D]
         L.orc_feq.argtypes = [cp, ctypes.c_double]
         L.orc_feq.restype = ctypes.c_double
         L.orc_init.argtypes = [cp, ctypes.c_int, _D, _D, _D, _D]
@@ -134,6 +138,19 @@ def advect_line(u: np.ndarray, d: int, beta: float) -> np.ndarray:
     return out
 
 
+def bspline(k: int, x: float) -> float:
+    """B^k_0(x) on the unit mesh (Section 1.2 recurrence)."""
+    return lib().orc_bspline(int(k), float(x))
+
+
+def advect_line_bspline(u: np.ndarray, k: int, beta: float) -> np.ndarray:
+    """Periodic B-spline interpolation of degree k of u at the feet i + beta."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    out = np.zeros_like(u)
+    lib().orc_advect_line_bspline(u.size, int(k), float(beta), _p(u), _p(out))
+    return out
+
+
 # ---------------------------------------------------------------- 2D model
 
 class Oracle:
@@ -154,6 +171,8 @@ class Oracle:
             c.feq_a[g], c.feq_c[g], c.feq_sigma[g] = w.feq_a[g], w.feq_c[g], w.feq_sigma[g]
         c.poisson = 1 if w.poisson == "trapezoid" else 0
         c.zero_mean = int(bool(w.zero_mean))
+        c.interp = 1 if w.interp == "bspline" else 0
+        c.merge_v = int(bool(w.merge_v))
         if w.drive is not None:
             d = w.drive
             c.drive_emax, c.drive_k, c.drive_omega = d.emax, d.k, d.omega

@@ -6,8 +6,8 @@
  *
  * What it computes, and where the paper defines it:
  *   - Strang splitting v(dt/2) -> x(dt) -> field update -> v(dt/2)
- *     (Section 1.1, steps 1-3; the last half step is not merged with the
- *     next step's first one).
+ *     (Section 1.1, steps 1-3; the last half step is merged with the next
+ *     step's first one only when merge_v is set).
  *   - Each constant advection u_i <- pi u(x_i - c dt) as the circulant
  *     product A u with A = C(a_0 .. a_{N-1}) (Section 1.2, eq. of matrix A),
  *     beta = -c dt / dx = b + s with b integer and s in [0, 1), and the
@@ -22,8 +22,11 @@
  *   - Diagnostics of Section 4: ||E||_2, the mass rho_hat_0, |rho_hat_1|,
  *     the L2 norm of f and the total energy.
  *   - Variants: the trapezoidal field solve with or without the zero-mean
- *     modification (Section 3.2), and the external drive of the KEEN-wave
- *     test (Section 4.3), which enters the v-advection as E - E_app.
+ *     modification (Section 3.2), the external drive of the KEEN-wave
+ *     test (Section 4.3), which enters the v-advection as E - E_app, the
+ *     B-spline interpolation A = M C^{-1} (Section 1.2) with the spline
+ *     coefficients from a dense LU solve, and merged v half-steps
+ *     (Section 1.1).
  */
 #include "vp_oracle.h"
 
@@ -110,6 +113,105 @@ void orc_advect_line(int n, int d, double beta, const double *u, double *out) {
     advect_strided(n, d, b, w, u, 1, out, 1);
 }
 
+/* ------------------------------------------------------------ B-splines */
+
+/* B^k_0(x) on the unit mesh x_i = i, from the degree recurrence of
+ * Section 1.2:
+ *   B^0_0 = indicator of [0, 1),
+ *   B^p_i(x) = (x - i)/p B^{p-1}_i(x) + (1 - (x - i - 1)/p) B^{p-1}_{i+1}(x).
+ * B^k_0(x) needs B^{k-1}_0 and B^{k-1}_1 at x, which need B^{k-2}_{0..2}, and
+ * so on down to B^0_{0..k}; level p keeps B^p_i(x) for i = 0 .. k - p. */
+double orc_bspline(int k, double x) {
+    double b[64];
+    for (int i = 0; i <= k; ++i) b[i] = (x >= i && x < i + 1) ? 1.0 : 0.0;
+    for (int p = 1; p <= k; ++p)
+        for (int i = 0; i <= k - p; ++i)
+            b[i] = (x - i) / p * b[i] + (1.0 - (x - i - 1.0) / p) * b[i + 1];
+    return b[0];
+}
+
+/* Collocation matrix of the periodic spline interpolation on n nodes,
+ * C = circulant(0, .., 0, B^k_0(x_1), .., B^k_0(x_k)) of Section 1.2:
+ * the spline sum_l c_l B^k_0(x - l) takes the value sum_l c_l B^k_0(i - l)
+ * at node i.  Factored in place as P C = L U (partial pivoting). */
+static void bspline_collocation_lu(int n, int k, double *a, int *piv) {
+    for (long i = 0; i < n; ++i)
+        for (long l = 0; l < n; ++l) a[i * n + l] = 0.0;
+    for (long i = 0; i < n; ++i)
+        for (int j = 1; j <= k; ++j) a[i * n + wrap(i - j, n)] += orc_bspline(k, (double)j);
+    for (int col = 0; col < n; ++col) {
+        int p = col;
+        for (int r = col + 1; r < n; ++r)
+            if (fabs(a[(long)r * n + col]) > fabs(a[(long)p * n + col])) p = r;
+        piv[col] = p;
+        if (p != col)
+            for (int l = 0; l < n; ++l) {
+                double t = a[(long)col * n + l];
+                a[(long)col * n + l] = a[(long)p * n + l];
+                a[(long)p * n + l] = t;
+            }
+        for (int r = col + 1; r < n; ++r) {
+            double m = a[(long)r * n + col] / a[(long)col * n + col];
+            a[(long)r * n + col] = m;
+            for (int l = col + 1; l < n; ++l) a[(long)r * n + l] -= m * a[(long)col * n + l];
+        }
+    }
+}
+
+/* Solves C x = rhs with the factors above; x may alias rhs. */
+static void lu_solve(int n, const double *a, const int *piv, const double *rhs, double *x) {
+    if (x != rhs) memcpy(x, rhs, sizeof(double) * n);
+    /* the factorization swapped whole rows, multipliers included: permute
+     * the right-hand side first, then substitute */
+    for (int col = 0; col < n; ++col) {
+        int p = piv[col];
+        if (p != col) {
+            double t = x[col];
+            x[col] = x[p];
+            x[p] = t;
+        }
+    }
+    for (int col = 0; col < n; ++col)
+        for (int r = col + 1; r < n; ++r) x[r] -= a[(long)r * n + col] * x[col];
+    for (int r = n - 1; r >= 0; --r) {
+        double acc = x[r];
+        for (int l = r + 1; l < n; ++l) acc -= a[(long)r * n + l] * x[l];
+        x[r] = acc / a[(long)r * n + r];
+    }
+}
+
+/* One line of the B-spline advection A = M C^{-1} (Section 1.2): the spline
+ * coefficients c solve C c = u, and the spline is evaluated at the feet
+ * x_i + beta = x_{i+b} + s, where it equals
+ *   sum_{j=0}^{k} B^k_0(x_{j+s}) c_{i+b-j}   (the entries m_{b-j} of M).
+ * u and out are strided; work holds n doubles. */
+static void bspline_line(int n, int k, long b, double s, const double *lu, const int *piv,
+                         const double *u, long us, double *out, long os, double *work) {
+    double m[64];
+    for (int j = 0; j <= k; ++j) m[j] = orc_bspline(k, j + s);
+    for (int i = 0; i < n; ++i) work[i] = u[(long)i * us];
+    lu_solve(n, lu, piv, work, work);
+    for (long i = 0; i < n; ++i) {
+        double acc = 0.0;
+        for (int j = 0; j <= k; ++j) acc += m[j] * work[wrap(i + b - j, n)];
+        out[i * os] = acc;
+    }
+}
+
+void orc_advect_line_bspline(int n, int k, double beta, const double *u, double *out) {
+    long b;
+    double s;
+    double *lu = (double *)malloc(sizeof(double) * (size_t)n * n);
+    int *piv = (int *)malloc(sizeof(int) * n);
+    double *work = (double *)malloc(sizeof(double) * n);
+    orc_split_shift(beta, &b, &s);
+    bspline_collocation_lu(n, k, lu, piv);
+    bspline_line(n, k, b, s, lu, piv, u, 1, out, 1, work);
+    free(lu);
+    free(piv);
+    free(work);
+}
+
 static double dx_of(const orc_cfg *c) { return c->L / c->nx; }
 static double dv_of(const orc_cfg *c) { return (c->vmax - c->vmin) / c->nv; }
 static double v_of(const orc_cfg *c, int j) { return c->vmin + j * dv_of(c); }
@@ -140,37 +242,63 @@ void orc_init(const orc_cfg *c, int nmodes, const double *amp, const double *kx,
 }
 
 /* x-advection by dt (Section 1.1, step 2): for each v_j, c = v_j. */
-void orc_advect_x(const orc_cfg *c, double dt, const double *f, double *out) {
-    const int d = (c->degree - 1) / 2;
-    const double dx = dx_of(c);
-#pragma omp parallel for schedule(static)
-    for (int j = 0; j < c->nv; ++j) {
-        long b;
-        double s;
-        double w[64];
-        orc_split_shift(-v_of(c, j) * dt / dx, &b, &s);
-        orc_lagrange_weights(d, s, w);
-        advect_strided(c->nx, d, b, w, f + j, c->nv, out + j, c->nv);
-    }
+/* Lines of one sweep: nl lines of length n, line l starting at base + l ls
+ * with element stride es; beta(l) gives the normalized shift of line l. */
+typedef double (*beta_fn)(const orc_cfg *c, const double *E, double arg, int l);
+
+static double beta_x(const orc_cfg *c, const double *E, double dt, int j) {
+    (void)E;
+    return -v_of(c, j) * dt / dx_of(c);
 }
 
-/* v-advection by tau with field E (Section 1.1, steps 1 and 3; delta f form of
- * Section 3.1): for each x_i, c = E_i. */
-void orc_advect_v(const orc_cfg *c, const double *E, double tau, const double *f, double *out) {
+static double beta_v(const orc_cfg *c, const double *E, double tau, int i) {
+    const double Ei = c->field_zero ? 0.0 : E[i];
+    return -Ei * tau / dv_of(c);
+}
+
+static void advect_lines(const orc_cfg *c, int n, int nl, long ls, long es, beta_fn beta,
+                         const double *E, double arg, const double *f, double *out) {
     const int d = (c->degree - 1) / 2;
-    const double dv = dv_of(c);
+    double *lu = NULL;
+    int *piv = NULL;
+    if (c->interp == 1) {
+        lu = (double *)malloc(sizeof(double) * (size_t)n * n);
+        piv = (int *)malloc(sizeof(int) * n);
+        bspline_collocation_lu(n, c->degree, lu, piv);
+    }
+#pragma omp parallel
+    {
+        double *work = (double *)malloc(sizeof(double) * n);
+#pragma omp for schedule(static)
+        for (int l = 0; l < nl; ++l) {
+            long b;
+            double s;
+            double w[64];
+            orc_split_shift(beta(c, E, arg, l), &b, &s);
+            if (c->interp == 1) {
+                bspline_line(n, c->degree, b, s, lu, piv, f + l * ls, es, out + l * ls, es, work);
+            } else {
+                orc_lagrange_weights(d, s, w);
+                advect_strided(n, d, b, w, f + l * ls, es, out + l * ls, es);
+            }
+        }
+        free(work);
+    }
+    free(lu);
+    free(piv);
+}
+
+void orc_advect_x(const orc_cfg *c, double dt, const double *f, double *out) {
+    advect_lines(c, c->nx, c->nv, 1, c->nv, beta_x, NULL, dt, f, out);
+}
+
+void orc_advect_v(const orc_cfg *c, const double *E, double tau, const double *f, double *out) {
+    advect_lines(c, c->nv, c->nx, c->nv, 1, beta_v, E, tau, f, out);
+    if (c->deltaf) {
 #pragma omp parallel for schedule(static)
-    for (int i = 0; i < c->nx; ++i) {
-        long b;
-        double s;
-        double w[64];
-        const double Ei = c->field_zero ? 0.0 : E[i];
-        orc_split_shift(-Ei * tau / dv, &b, &s);
-        orc_lagrange_weights(d, s, w);
-        const double *u = f + (long)i * c->nv;
-        double *o = out + (long)i * c->nv;
-        advect_strided(c->nv, d, b, w, u, 1, o, 1);
-        if (c->deltaf) {
+        for (int i = 0; i < c->nx; ++i) {
+            const double Ei = c->field_zero ? 0.0 : E[i];
+            double *o = out + (long)i * c->nv;
             for (int j = 0; j < c->nv; ++j) {
                 double v = v_of(c, j);
                 o[j] += orc_feq(c, v - tau * Ei) - orc_feq(c, v);
@@ -179,7 +307,6 @@ void orc_advect_v(const orc_cfg *c, const double *E, double tau, const double *f
     }
 }
 
-/* rho_i = int f dv by the rectangle rule; delta f adds the f_eq integral. */
 void orc_rho(const orc_cfg *c, const double *f, double *rho) {
     const double dv = dv_of(c);
     double feq_sum = 0.0;
@@ -318,26 +445,27 @@ static void advect_v_driven(const orc_cfg *c, const double *E, double t, double 
     orc_advect_v(&cc, Etot, tau, f, out);
 }
 
+/* v-advection by tau with the field E - E_app(t, x_i) (plain E without a
+ * drive). */
+static void advect_v_at(const orc_cfg *c, const double *E, double t, double tau,
+                        const double *f, double *out, double *Etot) {
+    if (c->drive_emax != 0.0) advect_v_driven(c, E, t, tau, f, out, Etot);
+    else orc_advect_v(c, E, tau, f, out);
+}
+
 /* One Strang step (Section 1.1) from time t.  f, E hold f^n, E^n on entry
  * and f^{n+1}, E^{n+1} on exit; rho receives the density the new field was
  * solved from; tmp has nx*nv doubles.  With a drive, the first half step
  * uses E^n - E_app(t^n) and the second E^{n+1} - E_app(t^{n+1}). */
 void orc_step(const orc_cfg *c, double t, double dt, double *f, double *E, double *rho, double *tmp) {
     const long cells = (long)c->nx * c->nv;
-    if (c->drive_emax != 0.0) {
-        double *Etot = (double *)malloc(sizeof(double) * c->nx);
-        advect_v_driven(c, E, t, 0.5 * dt, f, tmp, Etot);
-        orc_advect_x(c, dt, tmp, f);
-        orc_field(c, f, E, rho);
-        advect_v_driven(c, E, t + dt, 0.5 * dt, f, tmp, Etot);
-        free(Etot);
-    } else {
-        orc_advect_v(c, E, 0.5 * dt, f, tmp);
-        orc_advect_x(c, dt, tmp, f);
-        orc_field(c, f, E, rho);
-        orc_advect_v(c, E, 0.5 * dt, f, tmp);
-    }
+    double *Etot = (double *)malloc(sizeof(double) * c->nx);
+    advect_v_at(c, E, t, 0.5 * dt, f, tmp, Etot);
+    orc_advect_x(c, dt, tmp, f);
+    orc_field(c, f, E, rho);
+    advect_v_at(c, E, t + dt, 0.5 * dt, f, tmp, Etot);
     memcpy(f, tmp, sizeof(double) * cells);
+    free(Etot);
 }
 
 /* ||E||_2 = (dx sum E^2)^{1/2}; rho_hat_0 = mean rho; |rho_hat_1| with
@@ -376,14 +504,32 @@ void orc_diag_moments(const orc_cfg *c, const double *f, const double *E, double
 
 /* nsteps Strang steps from time t0; diag (3 doubles per step, may be NULL)
  * receives ||E^{n+1}||_2, rho_hat_0 and |rho_hat_1| after each step. */
+/* nsteps Strang steps from time t0.  With merge_v, the half step that ends
+ * step n and the half step that starts step n+1 use the same field
+ * E^{n+1} - E_app(t^{n+1}), so they are applied as one v-advection by dt
+ * (Section 1.1); the run still starts and ends with a half step, so f is at
+ * a full time level on return. */
 void orc_run(const orc_cfg *c, double t0, double dt, int nsteps, double *f, double *E, double *diag) {
     const long cells = (long)c->nx * c->nv;
     double *tmp = (double *)malloc(sizeof(double) * cells);
     double *rho = (double *)malloc(sizeof(double) * c->nx);
+    double *Etot = (double *)malloc(sizeof(double) * c->nx);
     for (int n = 0; n < nsteps; ++n) {
-        orc_step(c, t0 + n * dt, dt, f, E, rho, tmp);
+        const double t = t0 + n * dt;
+        if (!c->merge_v) {
+            orc_step(c, t, dt, f, E, rho, tmp);
+        } else {
+            if (n == 0) {
+                advect_v_at(c, E, t, 0.5 * dt, f, tmp, Etot);
+                memcpy(f, tmp, sizeof(double) * cells);
+            }
+            orc_advect_x(c, dt, f, tmp);
+            orc_field(c, tmp, E, rho);
+            advect_v_at(c, E, t + dt, n == nsteps - 1 ? 0.5 * dt : dt, tmp, f, Etot);
+        }
         if (diag) orc_diag_field(c, rho, E, diag + 3L * n);
     }
     free(tmp);
     free(rho);
+    free(Etot);
 }

@@ -7,8 +7,9 @@
  * loads or calls it.  It shares no code, header, table or constant with the
  * HIP library.
  *
- * Every advection is the direct circulant stencil of the paper's Lagrange
- * 2d+1 interpolation (Section 1.2): no FFT is used anywhere.  The Poisson
+ * Every advection is the direct circulant product of the paper's Lagrange
+ * 2d+1 interpolation, or of its B-spline interpolation by a dense solve of
+ * the collocation system (Section 1.2): no FFT is used anywhere.  The Poisson
  * solve is a direct O(Nx^2) DFT with mode 0 (and the Nyquist mode) set to
  * zero (Section 3.2, Fourier variant).
  *
@@ -37,6 +38,8 @@ typedef struct {
     /* external drive E_app(t, x) = emax k a(t) sin(k x - omega t) (Section 4.3);
      * emax = 0 switches it off */
     double drive_emax, drive_k, drive_omega, drive_t0, drive_tl, drive_tr, drive_twl, drive_twr;
+    int interp;        /* 0: Lagrange 2d+1; 1: B-spline of degree k = degree (Section 1.2) */
+    int merge_v;       /* 1: orc_run merges the v half-steps of consecutive steps (Section 1.1) */
 } orc_cfg;
 
 int orc_num_threads(void);
@@ -46,6 +49,9 @@ void orc_lagrange_weights(int d, double s, double *w);
 void orc_split_shift(double beta, long *b, double *s);
 void orc_circulant_row(int n, int d, double beta, double *a);
 void orc_advect_line(int n, int d, double beta, const double *u, double *out);
+
+double orc_bspline(int k, double x);
+void orc_advect_line_bspline(int n, int k, double beta, const double *u, double *out);
 
 double orc_feq(const orc_cfg *c, double v);
 void orc_init(const orc_cfg *c, int nmodes, const double *amp, const double *kx,

@@ -347,3 +347,134 @@ def test_rho_modes_normalisation(orc):
     o.rho = rng.standard_normal(w.nx)
     ref = np.abs(np.fft.fft(o.rho))[1:8] / w.nx
     assert np.allclose(o.rho_modes(7), ref, rtol=0, atol=1e-14)
+
+
+# ----------------------------------------------------------------- B-splines (Section 1.2)
+
+@pytest.mark.parametrize("k", [0, 1, 2, 3, 5, 9, 17])
+def test_bspline_basis_matches_library(orc, k):
+    # The degree recurrence against scipy's B-spline on the knots 0 .. k+1.
+    from scipy.interpolate import BSpline
+    be = BSpline.basis_element(np.arange(k + 2.0), extrapolate=False)
+    xs = np.linspace(0.013, k + 0.987, 41)
+    got = np.array([orc.bspline(k, x) for x in xs])
+    assert np.max(np.abs(got - np.nan_to_num(be(xs)))) < 1e-14
+    assert orc.bspline(k, -0.5) == 0.0 and orc.bspline(k, k + 1.5) == 0.0
+
+
+@pytest.mark.parametrize("k", [1, 3, 7, 17])
+def test_bspline_partition_of_unity_and_symmetry(orc, k):
+    for s in (0.0, 0.21, 0.5, 0.93):
+        vals = [orc.bspline(k, s + j) for j in range(k + 1)]
+        assert abs(sum(vals) - 1.0) < 1e-14
+        assert abs(orc.bspline(k, s + 0.4) - orc.bspline(k, k + 1 - s - 0.4)) < 1e-14
+
+
+@pytest.mark.parametrize("beta", [0.3, -2.71, 5.5, 13.999])
+def test_cubic_spline_advection_matches_library(orc, beta):
+    # Periodic cubic spline interpolation evaluated at the feet i + beta.
+    from scipy.interpolate import CubicSpline
+    n = 32
+    u = np.random.default_rng(3).standard_normal(n)
+    ref = CubicSpline(np.arange(n + 1.0), np.append(u, u[0]), bc_type="periodic")(
+        (np.arange(n) + beta) % n)
+    assert np.max(np.abs(orc.advect_line_bspline(u, 3, beta) - ref)) < 1e-13
+
+
+@pytest.mark.parametrize("k,tol", [(5, 1e-13), (9, 1e-12), (17, 1e-11)])
+def test_high_degree_spline_advection_matches_library(orc, k, tol):
+    from scipy.interpolate import make_interp_spline
+    n = 48
+    u = np.random.default_rng(k).standard_normal(n)
+    for beta in (0.37, -7.2):
+        sp = make_interp_spline(np.arange(n + 1.0), np.append(u, u[0]), k=k, bc_type="periodic")
+        ref = sp((np.arange(n) + beta) % n)
+        assert np.max(np.abs(orc.advect_line_bspline(u, k, beta) - ref)) < tol
+
+
+def test_bspline_degree1_is_lagrange1(orc):
+    u = np.random.default_rng(5).standard_normal(24)
+    for beta in (0.25, -3.6, 11.01):
+        assert np.max(np.abs(orc.advect_line_bspline(u, 1, beta) - orc.advect_line(u, 0, beta))) < 1e-15
+
+
+@pytest.mark.parametrize("k", [3, 17])
+@pytest.mark.parametrize("beta", [0, 3, -7])
+def test_bspline_integer_shift_is_exact_roll(orc, k, beta):
+    # A spline interpolates its data: at an integer shift it returns them.
+    u = np.random.default_rng(9).standard_normal(40)
+    assert np.max(np.abs(orc.advect_line_bspline(u, k, beta) - np.roll(u, -beta))) < 1e-12
+
+
+def test_bspline_sweeps_apply_the_line_operator(orc):
+    # 2-D sweeps with interp = bspline apply the pinned line operator to every line.
+    w = workloads.landau_weak().replace(nx=32, nv=64, interp="bspline", degree=3)
+    o = orc.Oracle(w).init()
+    f0 = o.f.copy()
+    o.advect_x(0.37)
+    for j in (0, 17, 63):
+        beta = -(w.vmin + j * o.dv) * 0.37 / o.dx
+        assert np.max(np.abs(o.f[:, j] - orc.advect_line_bspline(f0[:, j], 3, beta))) < 1e-14
+    o.f = f0.copy()
+    o.advect_v(0.5)
+    for i in (0, 5, 31):
+        beta = -o.E[i] * 0.5 / o.dv
+        assert np.max(np.abs(o.f[i] - orc.advect_line_bspline(f0[i], 3, beta))) < 1e-14
+
+
+def test_bspline_landau_rate(orc):
+    # Cubic splines resolve weak Landau damping like LAG17 (Section 4.1 rate).
+    w = workloads.landau_weak().replace(interp="bspline", degree=3)
+    o = orc.Oracle(w).init()
+    d = o.step(w.nsteps)
+    t = (np.arange(w.nsteps) + 1) * w.dt
+    gamma, omega, _ = orc.landau_fit(t, d[:, 0])
+    assert abs(-gamma - _paper()["gamma"]) / _paper()["gamma"] < 0.05
+    assert abs(omega - 1.4156) / 1.4156 < 0.01
+
+
+# ------------------------------------------------------- merged v half-steps (Section 1.1)
+
+def test_merged_single_step_is_the_strang_step(orc):
+    # With one step there is nothing to merge.
+    w = workloads.landau_weak()
+    a = orc.Oracle(w).init()
+    b = orc.Oracle(w.replace(merge_v=True)).init()
+    a.step(1)
+    b.step(1)
+    assert np.array_equal(a.f, b.f) and np.array_equal(a.E, b.E)
+
+
+def test_merged_free_streaming_is_unchanged(orc):
+    # E = 0: every v-advection is the identity, merged or not.
+    w = workloads.free_streaming(32, 32, 8)
+    a = orc.Oracle(w).init()
+    b = orc.Oracle(w.replace(merge_v=True)).init()
+    a.step(8)
+    b.step(8)
+    assert np.array_equal(a.f, b.f)
+
+
+def test_merged_differs_at_interpolation_error_level(orc):
+    # Two half-shifts vs one full shift differ by the interpolation error:
+    # far below the solution scale for LAG17 on smooth data, much larger for LAG3.
+    diffs = {}
+    for deg in (3, 17):
+        w = workloads.landau_weak().replace(degree=deg)
+        a = orc.Oracle(w).init()
+        b = orc.Oracle(w.replace(merge_v=True)).init()
+        a.step(20)
+        b.step(20)
+        diffs[deg] = np.max(np.abs(a.f - b.f)) / np.max(np.abs(a.f))
+    assert 0.0 < diffs[17] < 1e-9
+    assert diffs[3] > 10.0 * diffs[17]
+
+
+def test_merged_landau_rate(orc):
+    w = workloads.landau_weak().replace(merge_v=True)
+    o = orc.Oracle(w).init()
+    d = o.step(w.nsteps)
+    t = (np.arange(w.nsteps) + 1) * w.dt
+    gamma, omega, _ = orc.landau_fit(t, d[:, 0])
+    assert abs(-gamma - _paper()["gamma"]) / _paper()["gamma"] < 0.05
+    assert abs(omega - 1.4156) / 1.4156 < 0.01

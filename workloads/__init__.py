@@ -26,7 +26,7 @@ import numpy as np
 
 INV_SQRT_2PI = 1.0 / math.sqrt(2.0 * math.pi)
 
-PRECISIONS = ("fp64_plain", "fp32_deltaf", "fp64_deltaf")
+PRECISIONS = ("fp64_plain", "fp32_deltaf", "fp64_deltaf", "fp32_plain")
 
 
 @dataclasses.dataclass(frozen=True)
@@ -65,6 +65,8 @@ class Workload:
     poisson: str = "fourier"        # or "trapezoid"
     zero_mean: bool = True          # trapezoid only
     drive: Optional[Drive] = None
+    interp: str = "lagrange"        # or "bspline" (odd degree k = degree)
+    merge_v: bool = False           # merge the v half-steps of consecutive steps
 
     @property
     def cells(self) -> int:
