@@ -46,6 +46,12 @@ extern "C" {
 #define VOG_FP64_PLAIN   0  /* f stored and advected in FP64 */
 #define VOG_FP32_DELTAF  1  /* delta f = f - f_eq stored and advected in FP32 (Section 3.1) */
 #define VOG_FP64_DELTAF  2  /* delta f in FP64 */
+#define VOG_FP32_PLAIN   3  /* f stored and advected in FP32 without the delta-f split: the
+                               single-precision variant the paper compares against (Section 4.1) */
+
+#define VOG_INTERP_LAGRANGE 0  /* Lagrange 2d+1 interpolation (Section 1.2) */
+#define VOG_INTERP_BSPLINE  1  /* B-spline interpolation of odd degree k = 2d+1 (Section 1.2):
+                                  A = M C^{-1}, C the collocation circulant */
 
 #define VOG_POISSON_FOURIER   0  /* Fourier solve, mode 0 set to zero (Section 3.2) */
 #define VOG_POISSON_TRAPEZOID 1  /* trapezoidal rule, with or without the zero-mean step (Section 3.2) */
@@ -62,8 +68,8 @@ typedef struct vog_config {
     int nx, nv;          /* powers of two in [8, 4096] */
     double L;            /* x in [0, L), L > 0 */
     double vmin, vmax;   /* vmin < vmax */
-    int degree;          /* odd Lagrange degree 2d+1, 1 <= degree <= min(17, nx-1, nv-1) */
-    int precision;       /* VOG_FP64_PLAIN, VOG_FP32_DELTAF or VOG_FP64_DELTAF */
+    int degree;          /* odd interpolation degree 2d+1, 1 <= degree <= min(17, nx-1, nv-1) */
+    int precision;       /* VOG_FP64_PLAIN, VOG_FP32_DELTAF, VOG_FP64_DELTAF or VOG_FP32_PLAIN */
     int poisson;         /* VOG_POISSON_FOURIER or VOG_POISSON_TRAPEZOID */
     int field;           /* VOG_FIELD_SELF_CONSISTENT or VOG_FIELD_ZERO */
     /* f_eq(v) = sum_g feq_a[g] exp(-(v - feq_c[g])^2 / (2 feq_sigma[g]^2)),
@@ -86,6 +92,18 @@ typedef struct vog_config {
      * half step at t^n, the second at t^{n+1}).  drive_emax = 0: no drive;
      * otherwise twl, twr > 0 and drive_k, drive_omega finite. */
     double drive_emax, drive_k, drive_omega, drive_t0, drive_tl, drive_tr, drive_twl, drive_twr;
+    /* VOG_INTERP_LAGRANGE or VOG_INTERP_BSPLINE; both use the same 2d+2
+     * taps per line, B-splines also divide by the collocation symbol. */
+    int interp;
+    /* 1: inside one vog_step / vog_step_batch call, the v half-step that
+     * ends step n and the one that starts step n+1 (same field
+     * E^{n+1} - E_app(t^{n+1})) run as one v-advection by dt (Section 1.1):
+     * 2 sweeps per step instead of 3.  Every call still starts and ends
+     * with a half step, so f is at a full time level between calls; results
+     * differ from the unmerged scheme at the interpolation-error level and
+     * depend on how a run is cut into calls.  L2 and energy are computed on
+     * the last step of a call only. */
+    int merge_v;
 } vog_config;
 
 /* One record per time step, written on the device by the field solve. */

@@ -34,6 +34,41 @@ __device__ __forceinline__ double lagrange_weight(int d, int q, double s) {
     return num / den;
 }
 
+// B-spline coefficient of node q for the fractional shift s in [0, 1)
+// (Section 1.2, degree k = 2d+1): B^k(d + 1 - q + s), B^k the uniform
+// B-spline of degree k on [0, k+1).  The values B^p(s + j), j = 0..p, are
+// raised one degree at a time with B^p(x) = x/p B^{p-1}(x) +
+// (p+1-x)/p B^{p-1}(x-1); the loops are unrolled to the largest degree so
+// that the table stays in registers.  Not inlined: it runs once per line
+// pair, and as a call its registers do not add to those of the transform.
+__device__ __attribute__((noinline)) double bspline_weight(int d, int q, double s) {
+    if (q < -d || q > d + 1) return 0.0;
+    const int k = 2 * d + 1;
+    double b[kTaps];
+    static_for<0, kTaps>([&](auto jc) { b[decltype(jc)::value] = 0.0; });
+    b[0] = 1.0;
+    static_for<1, kTaps>([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        if (p <= k) {
+            constexpr double ip = 1.0 / (double)p;
+            static_for<0, p + 1>([&](auto jc) {
+                constexpr int j = p - decltype(jc)::value;  // descending: b[j-1] still of degree p-1
+                const double x = s + (double)j;
+                double v = x * ip * b[j];
+                if constexpr (j > 0) v = fma((double)(p + 1) * ip - x * ip, b[j - 1], v);
+                b[j] = v;
+            });
+        }
+    });
+    const int jq = d + 1 - q;
+    double r = 0.0;
+    static_for<0, kTaps>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        if (j == jq) r = b[j];
+    });
+    return r;
+}
+
 // beta = b + s with b integer and s in [0, 1).  A non-finite or absurdly
 // large beta (a diverged field) gives b = 0 and s = NaN, so the line becomes
 // NaN and the failure shows in the field's finite flag.
@@ -109,11 +144,12 @@ __device__ __forceinline__ void deltaf_source(const SimDev &S, double tauE, int 
 // folds the scale of the inverse FFT).  Threads t = 0.. of the pair share the
 // 2 x kTaps values; visible to the pair after the next barrier.
 template <typename T, int N, int TPF>
-__device__ __forceinline__ void pair_weights(int d, double sA, double sB, int t, T *wP, T *wQ) {
+__device__ __forceinline__ void pair_weights(int d, int interp, double sA, double sB, int t, T *wP,
+                                             T *wQ) {
     for (int qi = t; qi < kTaps; qi += TPF) {
         const int q = qi - kDMax;
-        const double wa = lagrange_weight(d, q, sA);
-        const double wb = lagrange_weight(d, q, sB);
+        const double wa = interp ? bspline_weight(d, q, sA) : lagrange_weight(d, q, sA);
+        const double wb = interp ? bspline_weight(d, q, sB) : lagrange_weight(d, q, sB);
         const double sc = 0.5 / (double)N;
         wP[qi] = (T)((wa + wb) * sc);
         wQ[qi] = (T)((wa - wb) * sc);
@@ -126,13 +162,16 @@ __device__ __forceinline__ void pair_weights(int d, double sA, double sB, int t,
 // The symbol of the fractional-shift kernel for the modes m = t + k TPF is
 //   S_m = sum_q w_q exp(2 pi i m q / N) = DFT_R^+ (H)[k],
 //   H_c = sum_{q = c mod R} w_q exp(2 pi i t q / N),
-// evaluated for the combined weights wP and wQ.  All threads of the block
-// must call this (it contains block barriers).
+// evaluated for the combined weights wP and wQ.  For B-splines (iden not
+// null) the packed product of mode m is divided by the collocation symbol:
+// Y_m *= iden[m].  All threads of the block must call this (it contains
+// block barriers).
 template <typename T, int N, bool RELOAD_TW, int R = fft_regs(N)>
 __device__ __forceinline__ void pair_transform(cx<T> (&v)[R], cx<T> (&Y)[R], int t, T *lre, T *lim,
                                                const cx<T> *__restrict__ tw,
                                                const cx<T> *eps,
-                                               const T *wP, const T *wQ) {
+                                               const T *wP, const T *wQ,
+                                               const T *__restrict__ iden) {
     using F = Fft<T, N>;
     constexpr int TPF = F::TPF;
     static_assert(R == F::R, "register count");
@@ -217,6 +256,14 @@ __device__ __forceinline__ void pair_transform(cx<T> (&v)[R], cx<T> (&Y)[R], int
             Y[k] = Y[k] + cmul(H[k], cx<T>{v[ip].re, -v[ip].im});
         });
     }
+    if (iden) {
+        static_for<0, R>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            const T sc = iden[t + k * TPF];
+            Y[k].re *= sc;
+            Y[k].im *= sc;
+        });
+    }
 
     // RELOAD_TW: re-read the twiddle rows instead of keeping the forward
     // pass's rows live in registers (for kernels with a tight register budget).
@@ -230,7 +277,8 @@ __device__ __forceinline__ void pair_transform(cx<T> (&v)[R], cx<T> (&Y)[R], int
 //
 // Two real lines A, B are packed as z = uA + i uB and transformed together.
 // With beta = b + s (b integer, s in [0,1)), the circulant A of Section 1.2 is
-// the cyclic shift by b composed with the Lagrange kernel w_q(s), q = -d..d+1.
+// the cyclic shift by b composed with the kernel w_q(s), q = -d..d+1 (Lagrange,
+// or B-spline taps followed by the division by the collocation symbol).
 // The kernel is applied in Fourier space through its symbol and the shift by
 // b is applied exactly on the store (index j -> j - b mod N).
 template <typename T, int N, int KIND>
@@ -277,7 +325,7 @@ __global__ __launch_bounds__(256) void sweep_kernel(const Batch b) {
     double sA, sB;
     split_shift(betaA, bA, sA);
     split_shift(betaB, bB, sB);
-    pair_weights<T, N, TPF>(S.d, sA, sB, t, wsh[slot][0], wsh[slot][1]);
+    pair_weights<T, N, TPF>(S.d, S.interp, sA, sB, t, wsh[slot][0], wsh[slot][1]);
 
     // Load the two lines packed as z = uA + i uB.
     cx<T> v[R];
@@ -288,7 +336,8 @@ __global__ __launch_bounds__(256) void sweep_kernel(const Batch b) {
     });
 
     cx<T> Y[R];
-    pair_transform<T, N, (sizeof(T) == 8)>(v, Y, t, lre, lim, tw, eps, wsh[slot][0], wsh[slot][1]);
+    pair_transform<T, N, (sizeof(T) == 8)>(v, Y, t, lre, lim, tw, eps, wsh[slot][0], wsh[slot][1],
+                                           (const T *)(KIND == 0 ? S.iden_v : S.iden_x));
 
     if (!active) return;
 
@@ -359,6 +408,17 @@ __global__ __launch_bounds__((kFusedThreads<T, N>)) void xsweep_fused_kernel(con
     T *f = (T *)S.f;
     const int tid = threadIdx.x;
 
+    // Shifts and weights first, while no tile data is live in registers.
+    const int slot = tid / TPF;
+    const int t = tid % TPF;
+    const int lineA = j0 + 2 * slot, lineB = lineA + 1;
+    const double dt = b.a[blockIdx.y];
+    long long bA, bB;
+    double sA, sB;
+    split_shift(-(S.vmin + lineA * S.dv) * dt * S.inv_dx, bA, sA);
+    split_shift(-(S.vmin + lineB * S.dv) * dt * S.inv_dx, bB, sB);
+    pair_weights<T, N, TPF>(S.d, S.interp, sA, sB, t, wsh[slot][0], wsh[slot][1]);
+
     // Tile to LDS: column c of the tile is line j0 + c; pair c / 2 keeps line
     // 2p in its real array and line 2p + 1 in its imaginary array.
     static_for<0, C::ITER>([&](auto kc) {
@@ -382,22 +442,12 @@ __global__ __launch_bounds__((kFusedThreads<T, N>)) void xsweep_fused_kernel(con
         });
     });
 
-    const int slot = tid / TPF;
-    const int t = tid % TPF;
     T *lre = lds + (2 * slot) * C::LDSP;
     T *lim = lre + C::LDSP;
     const cx<T> *tw = (const cx<T> *)S.tw_x;
     const cx<T> *eps = (const cx<T> *)S.eps_x + t * kEpsRow;
-    const int lineA = j0 + 2 * slot, lineB = lineA + 1;
 
-    const double dt = b.a[blockIdx.y];
-    long long bA, bB;
-    double sA, sB;
-    split_shift(-(S.vmin + lineA * S.dv) * dt * S.inv_dx, bA, sA);
-    split_shift(-(S.vmin + lineB * S.dv) * dt * S.inv_dx, bB, sB);
-    pair_weights<T, N, TPF>(S.d, sA, sB, t, wsh[slot][0], wsh[slot][1]);
-
-    __syncthreads();  // tile in LDS
+    __syncthreads();  // tile and weights in LDS
     cx<T> v[R];
     {
         const int pt = F::pad(t);
@@ -409,7 +459,8 @@ __global__ __launch_bounds__((kFusedThreads<T, N>)) void xsweep_fused_kernel(con
     }
 
     cx<T> Y[R];
-    pair_transform<T, N, true>(v, Y, t, lre, lim, tw, eps, wsh[slot][0], wsh[slot][1]);
+    pair_transform<T, N, true>(v, Y, t, lre, lim, tw, eps, wsh[slot][0], wsh[slot][1],
+                               (const T *)S.iden_x);
 
     // Shifted result back to LDS: unshifted index j goes to position (j - b) mod N.
     __syncthreads();

@@ -71,8 +71,57 @@ void unit_roots(int n, std::vector<double> &re, std::vector<double> &im) {
 }
 
 struct Layout {
-    size_t f, g, E, Eeff, part, rho, mom, tw_x, tw_v, eps_x, eps_v, tw_x64, invk, feq_g, feq64, ring, dev, total;
+    size_t f, g, E, Eeff, part, rho, mom, tw_x, tw_v, eps_x, eps_v, tw_x64, invk, iden_x, iden_v,
+        feq_g, feq64, ring, dev, total;
 };
+
+bool prec_fp64(const vog_config &c) {
+    return c.precision == VOG_FP64_PLAIN || c.precision == VOG_FP64_DELTAF;
+}
+
+bool prec_deltaf(const vog_config &c) {
+    return c.precision == VOG_FP32_DELTAF || c.precision == VOG_FP64_DELTAF;
+}
+
+// B^k(j) at the integers j = 0 .. k+1 of the uniform B-spline of degree k
+// on [0, k+1), from the degree recurrence B^p(x) = x/p B^{p-1}(x) +
+// (p+1-x)/p B^{p-1}(x-1) (Section 1.2), FP64.
+std::vector<double> bspline_at_integers(int k) {
+    std::vector<double> b(k + 2, 0.0), nb(k + 2, 0.0);
+    b[0] = 1.0;  // B^0 is the indicator of [0, 1): B^0(j) = [j == 0]
+    for (int p = 1; p <= k; ++p) {
+        for (int j = 0; j <= k + 1; ++j) {
+            const double x = (double)j;
+            nb[j] = x / p * b[j] + (j > 0 ? (p + 1 - x) / p * b[j - 1] : 0.0);
+        }
+        b.swap(nb);
+    }
+    return b;
+}
+
+// 1 / D_m, m < n, for B-spline interpolation of degree k = 2d+1 on n nodes:
+// the collocation circulant has the symbol e^{-i theta (d+1)} D_m with
+// D_m = sum_{j=1..k} B^k(j) cos(theta_m (j - d - 1)), theta_m = 2 pi m / n,
+// which is real and positive for odd k.  The sweep multiplies the packed
+// product by 1 / D_m; the phase e^{i theta (d+1)} is folded into the taps
+// w_q = B^k(d + 1 - q + s), q = -d .. d+1.
+std::vector<double> bspline_inverse_symbol(int n, int k) {
+    const int d = (k - 1) / 2;
+    const std::vector<double> bj = bspline_at_integers(k);
+    std::vector<double> re, im;
+    unit_roots(n, re, im);  // exp(i pi l / n), l < 2n
+    std::vector<double> out(n);
+    for (int m = 0; m < n; ++m) {
+        double acc = 0.0;
+        for (int j = 1; j <= k; ++j) {
+            const long long a = (long long)m * (j - d - 1);
+            const long long r = ((a % n) + n) % n;
+            acc += bj[j] * re[2 * r];
+        }
+        out[m] = 1.0 / acc;
+    }
+    return out;
+}
 
 // How the x-sweep reaches the x-lines of the v-fastest array f[nx][nv]:
 // tiles of whole x-lines staged through LDS when a tile fits the grid,
@@ -80,15 +129,16 @@ struct Layout {
 enum XMode { X_TRANSPOSED = 0, X_TILED = 1 };
 
 XMode xsweep_mode(const vog_config &c) {
-    const int B = fused_lines_per_block(c.precision != VOG_FP32_DELTAF, c.nx);
+    const int B = fused_lines_per_block(prec_fp64(c), c.nx);
     return (B > 0 && c.nv >= B) ? X_TILED : X_TRANSPOSED;
 }
 
 bool uses_fused_xsweep(const vog_config &c) { return xsweep_mode(c) != X_TRANSPOSED; }
 
 Layout layout_of(const vog_config &c) {
-    const size_t es = c.precision == VOG_FP32_DELTAF ? 4 : 8;
+    const size_t es = prec_fp64(c) ? 8 : 4;
     const size_t cells = (size_t)c.nx * c.nv;
+    const bool spline = c.interp == VOG_INTERP_BSPLINE;
     const int nparts = (c.nv + kTile - 1) / kTile;
     Layout L{};
     size_t off = 0;
@@ -110,6 +160,8 @@ Layout layout_of(const vog_config &c) {
     L.eps_v = take(2 * es * kEpsRow * (c.nv / fft_regs(c.nv)));
     L.tw_x64 = take(2 * sizeof(double) * fft_tw_total(c.nx));
     L.invk = take(sizeof(double) * c.nx);
+    L.iden_x = take(spline ? es * c.nx : 0);
+    L.iden_v = take(spline ? es * c.nv : 0);
     L.feq_g = take(es * VOG_MAX_FEQ * c.nv);
     L.feq64 = take(sizeof(double) * c.nv);
     L.ring = take(sizeof(vog_diag) * kRingCap);
@@ -164,8 +216,11 @@ int validate(const vog_config *c) {
     if (c->degree > c->nx - 1 || c->degree > c->nv - 1)
         return fail(VOG_EINVAL, "degree must be <= min(nx, nv) - 1");
     if (c->precision != VOG_FP64_PLAIN && c->precision != VOG_FP32_DELTAF &&
-        c->precision != VOG_FP64_DELTAF)
+        c->precision != VOG_FP64_DELTAF && c->precision != VOG_FP32_PLAIN)
         return fail(VOG_EINVAL, "unknown precision");
+    if (c->interp != VOG_INTERP_LAGRANGE && c->interp != VOG_INTERP_BSPLINE)
+        return fail(VOG_EINVAL, "unknown interpolation");
+    if (c->merge_v != 0 && c->merge_v != 1) return fail(VOG_EINVAL, "merge_v must be 0 or 1");
     if (c->poisson != VOG_POISSON_FOURIER && c->poisson != VOG_POISSON_TRAPEZOID)
         return fail(VOG_EINVAL, "unknown Poisson solver");
     if (c->zero_mean != 0 && c->zero_mean != 1) return fail(VOG_EINVAL, "zero_mean must be 0 or 1");
@@ -516,27 +571,40 @@ int device_guard(vog_sim *s) {
     return VOG_OK;
 }
 
+// nsteps Strang steps (Section 1.1) of every sim, one grouped launch per
+// kernel kind and line length.  Sims with merge_v skip the opening half
+// step of steps 1 .. nsteps-1 and advect by dt at the end of steps
+// 0 .. nsteps-2 instead (the two half steps share the field).
 int step_sims(const std::vector<vog_sim *> &sims, const std::vector<double> &dt, int nsteps) {
     vog_sim *lead = sims[0];
-    std::vector<double> tau(sims.size());
-    for (size_t k = 0; k < sims.size(); ++k) tau[k] = 0.5 * dt[k];
     std::vector<int64_t> stepno(sims.size());
     std::vector<double> tnow(sims.size());
     for (int n = 0; n < nsteps; ++n) {
+        const bool last = n == nsteps - 1;
+        std::vector<vog_sim *> open;  // sims that start this step with a half step
+        std::vector<double> half, tau_end(sims.size());
         for (size_t k = 0; k < sims.size(); ++k) {
             stepno[k] = sims[k]->step + 1;
             tnow[k] = sims[k]->t + dt[k];
+            const bool merge = sims[k]->cfg.merge_v != 0;
+            if (!merge || n == 0) {
+                open.push_back(sims[k]);
+                half.push_back(0.5 * dt[k]);
+            }
+            tau_end[k] = (merge && !last) ? dt[k] : 0.5 * dt[k];
         }
         int rc;
-        if ((rc = run_sweep(lead, sims, tau, true)) != VOG_OK) return rc;
+        if (!open.empty() && (rc = run_sweep(lead, open, half, true)) != VOG_OK) return rc;
         if ((rc = x_advection(lead, sims, dt, true)) != VOG_OK) return rc;
         if ((rc = run_field(lead, sims, stepno, tnow)) != VOG_OK) return rc;
-        if ((rc = run_sweep(lead, sims, tau, true)) != VOG_OK) return rc;
+        if ((rc = run_sweep(lead, sims, tau_end, true)) != VOG_OK) return rc;
         std::vector<vog_sim *> msims;
         std::vector<int64_t> mstep;
         for (size_t k = 0; k < sims.size(); ++k) {
             const int every = sims[k]->cfg.moments_every;
-            if (every > 0 && stepno[k] % every == 0) {
+            // merged sims hold a full time level only after a call's last step
+            const bool level = !sims[k]->cfg.merge_v || last;
+            if (every > 0 && stepno[k] % every == 0 && level) {
                 msims.push_back(sims[k]);
                 mstep.push_back(stepno[k]);
             }
@@ -596,7 +664,7 @@ int vog_create(const vog_config *c, void *dev_workspace, size_t bytes, void *hip
     s->cfg = *c;
     s->lay = L;
     s->stream = (hipStream_t)hip_stream;
-    s->fp64 = c->precision != VOG_FP32_DELTAF;
+    s->fp64 = prec_fp64(*c);
     s->fused = uses_fused_xsweep(*c);
     s->xmode = xsweep_mode(*c);
     s->step = 0;
@@ -643,6 +711,9 @@ int vog_create(const vog_config *c, void *dev_workspace, size_t bytes, void *hip
     D.eps_x = s->ws + L.eps_x;
     D.eps_v = s->ws + L.eps_v;
     D.tw_x64 = (const double *)(s->ws + L.tw_x64);
+    D.iden_x = c->interp == VOG_INTERP_BSPLINE ? s->ws + L.iden_x : nullptr;
+    D.iden_v = c->interp == VOG_INTERP_BSPLINE ? s->ws + L.iden_v : nullptr;
+    D.interp = c->interp;
     D.invk = (const double *)(s->ws + L.invk);
     D.feq_g = s->ws + L.feq_g;
     D.feq64 = (const double *)(s->ws + L.feq64);
@@ -650,7 +721,7 @@ int vog_create(const vog_config *c, void *dev_workspace, size_t bytes, void *hip
     D.nx = nx;
     D.nv = nv;
     D.d = (c->degree - 1) / 2;
-    D.deltaf = c->precision != VOG_FP64_PLAIN;
+    D.deltaf = prec_deltaf(*c);
     D.field_zero = c->field == VOG_FIELD_ZERO;
     D.n_feq = c->n_feq;
     D.nparts = (nv + kTile - 1) / kTile;
@@ -696,7 +767,21 @@ int vog_create(const vog_config *c, void *dev_workspace, size_t bytes, void *hip
     const std::vector<double> tw64v = twiddle_rows<double>(nv);
     const std::vector<double> ep64x = eps_rows<double>(nx);
     const std::vector<double> ep64v = eps_rows<double>(nv);
-    std::vector<float> tw32x, tw32v, ep32x, ep32v, fg32;
+    std::vector<float> tw32x, tw32v, ep32x, ep32v, fg32, id32x, id32v;
+    std::vector<double> id64x, id64v;
+    if (c->interp == VOG_INTERP_BSPLINE) {
+        id64x = bspline_inverse_symbol(nx, c->degree);
+        id64v = bspline_inverse_symbol(nv, c->degree);
+        if (fp64) {
+            if ((rc = upload_vec(s->ws + L.iden_x, id64x, s->stream)) != VOG_OK) return bail(rc);
+            if ((rc = upload_vec(s->ws + L.iden_v, id64v, s->stream)) != VOG_OK) return bail(rc);
+        } else {
+            id32x.assign(id64x.begin(), id64x.end());
+            id32v.assign(id64v.begin(), id64v.end());
+            if ((rc = upload_vec(s->ws + L.iden_x, id32x, s->stream)) != VOG_OK) return bail(rc);
+            if ((rc = upload_vec(s->ws + L.iden_v, id32v, s->stream)) != VOG_OK) return bail(rc);
+        }
+    }
     if (fp64) {
         if ((rc = upload_vec(s->ws + L.tw_x, tw64x, s->stream)) != VOG_OK) return bail(rc);
         if ((rc = upload_vec(s->ws + L.tw_v, tw64v, s->stream)) != VOG_OK) return bail(rc);

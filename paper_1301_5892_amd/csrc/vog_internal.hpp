@@ -29,11 +29,13 @@ struct SimDev {
     const void *eps_x;  // [nx / 16][10] exp(2 pi i t q / nx), symbol table for the x-sweep
     const void *eps_v;  // [nv / 16][10] exp(2 pi i t q / nv)
     const double *tw_x64;  // FP64 twiddle rows for length nx (field solve)
+    const void *iden_x; // [nx] 1 / collocation symbol of the B-spline, storage precision (else null)
+    const void *iden_v; // [nv]
     const double *invk;    // [nx] 1 / (nx k_m), k_m = 2 pi mt / L; 0 at m = 0, nx/2 (field solve)
     const void *feq_g;  // [n_feq][nv] component values f_g(v_j), storage precision
     const double *feq64;    // [nv] f_eq(v_j), FP64
     vog_diag *ring;     // [kRingCap]
-    int nx, nv, d, deltaf, field_zero, n_feq, nparts, fp64, poisson, zero_mean;
+    int nx, nv, d, deltaf, field_zero, n_feq, nparts, fp64, poisson, zero_mean, interp;
     double drive_k;     // wavenumber of the external drive (0: none)
     double L, vmin, dx, dv, inv_dx, inv_dv;
     double feq_c[VOG_MAX_FEQ], feq_inv_s2[VOG_MAX_FEQ];

@@ -17,14 +17,17 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libvog.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, EBUSY = 0, -1, -2, -3, -4, -5
-FP64_PLAIN, FP32_DELTAF, FP64_DELTAF = 0, 1, 2
+FP64_PLAIN, FP32_DELTAF, FP64_DELTAF, FP32_PLAIN = 0, 1, 2, 3
+INTERP_LAGRANGE, INTERP_BSPLINE = 0, 1
 POISSON_FOURIER, POISSON_TRAPEZOID = 0, 1
 FIELD_SELF_CONSISTENT, FIELD_ZERO = 0, 1
 MAX_FEQ = 4
 NUM_KINDS = 7
 KIND_NAMES = ("sweep_v", "sweep_x", "transpose_vx", "transpose_xv_rho", "field", "moments",
               "rho_reduce")
-PRECISION = {"fp64_plain": FP64_PLAIN, "fp32_deltaf": FP32_DELTAF, "fp64_deltaf": FP64_DELTAF}
+PRECISION = {"fp64_plain": FP64_PLAIN, "fp32_deltaf": FP32_DELTAF, "fp64_deltaf": FP64_DELTAF,
+             "fp32_plain": FP32_PLAIN}
+INTERP = {"lagrange": INTERP_LAGRANGE, "bspline": INTERP_BSPLINE}
 
 
 class VogError(RuntimeError):
@@ -45,7 +48,8 @@ class Config(ctypes.Structure):
                 ("drive_emax", ctypes.c_double), ("drive_k", ctypes.c_double),
                 ("drive_omega", ctypes.c_double), ("drive_t0", ctypes.c_double),
                 ("drive_tl", ctypes.c_double), ("drive_tr", ctypes.c_double),
-                ("drive_twl", ctypes.c_double), ("drive_twr", ctypes.c_double)]
+                ("drive_twl", ctypes.c_double), ("drive_twr", ctypes.c_double),
+                ("interp", ctypes.c_int), ("merge_v", ctypes.c_int)]
 
 
 class Diag(ctypes.Structure):
@@ -152,6 +156,8 @@ def make_config(w, moments_every: int = 0, precision: Optional[str] = None) -> C
     for g in range(c.n_feq):
         c.feq_a[g], c.feq_c[g], c.feq_sigma[g] = w.feq_a[g], w.feq_c[g], w.feq_sigma[g]
     c.moments_every = moments_every
+    c.interp = INTERP[w.interp]
+    c.merge_v = int(bool(w.merge_v))
     return c
 
 
@@ -219,7 +225,7 @@ class Sim:
         return out
 
     def get_raw(self) -> np.ndarray:
-        es = 4 if self.cfg.precision == FP32_DELTAF else 8
+        es = 4 if self.cfg.precision in (FP32_DELTAF, FP32_PLAIN) else 8
         out = np.zeros((self.nx, self.nv), dtype=np.float32 if es == 4 else np.float64)
         eb = ctypes.c_int()
         _check(load().vog_get_raw(self.handle, out.ctypes.data_as(_P), out.nbytes,
