@@ -57,7 +57,7 @@ def parse():
                         "(16 large-grid FP32 sims hold 1 GiB of f); 0 skips this leg")
     p.add_argument("--summarize-rocprof", metavar="DIR", default=None,
                    help="write profiles/ summaries from the rocprofv3 CSV output under DIR "
-                        "(subfolders kt/, fetch/, write/ and kt.log, as in PROFILE_COMMANDS)")
+                        "(subfolders kt/, fetch/, write/, valu/ and kt.log, as in PROFILE_COMMANDS)")
     return p.parse_args()
 
 
@@ -221,6 +221,9 @@ PROFILE_COMMANDS = {
              "--steps 2 --warmup 1 --no-serving --no-cpu-baseline --dram-sims 0 --copy-calibration",
     "write": "rocprofv3 --pmc WRITE_SIZE -f csv -d {out}/write -o write -- python3 {root}/bench.py "
              "--steps 2 --warmup 1 --no-serving --no-cpu-baseline --dram-sims 0 --copy-calibration",
+    "valu": "rocprofv3 --pmc SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_BUSY_CU_CYCLES SQ_WAVE_CYCLES "
+            "SQ_INSTS_LDS SQ_WAIT_INST_LDS -f csv -d {out}/valu -o valu -- python3 {root}/bench.py "
+            "--steps 2 --warmup 1 --no-serving --no-cpu-baseline --dram-sims 0 --copy-calibration",
 }
 COPY_CALIBRATION_BYTES = 256 << 20
 
@@ -261,11 +264,13 @@ def _csv_rows(folder, suffix):
     return rows
 
 
-def _counter_per_kernel(folder):
-    """kernel name -> list of per-dispatch counter values (KiB)."""
+def _counter_per_kernel(folder, counter=None):
+    """kernel name -> list of per-dispatch values of one counter (all rows when
+    the file holds a single counter)."""
     out = {}
     for r in _csv_rows(folder, "counter_collection.csv"):
-        out.setdefault(r["kernel_name"], []).append(float(r["counter_value"]))
+        if counter is None or r["counter_name"] == counter:
+            out.setdefault(r["kernel_name"], []).append(float(r["counter_value"]))
     return out
 
 
@@ -376,8 +381,38 @@ def summarize_rocprof(folder, wname):
         fh.write("\n".join(lines) + "\n")
     with open(table_path, "w") as fh:
         json.dump(table, fh, indent=1, sort_keys=True)
+
+    # VALU issue: SQ_ACTIVE_INST_VALU counts one per wave64 VALU instruction
+    # (4 cycles of a 16-lane SIMD) and SQ_BUSY_CU_CYCLES counts cycles summed
+    # over CUs; a CU's 4 SIMDs issue at most one wave instruction per cycle
+    # between them, so ACTIVE_INST_VALU / BUSY_CU_CYCLES is the VALU busy
+    # fraction.
+    vdir = os.path.join(folder, "valu")
+    if os.path.isdir(vdir):
+        names = ("SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU", "SQ_BUSY_CU_CYCLES", "SQ_WAVE_CYCLES",
+                 "SQ_INSTS_LDS", "SQ_WAIT_INST_LDS")
+        per = {n: _counter_per_kernel(vdir, n) for n in names}
+        lines = [f"# VALU issue per kernel, {wname}", "", "Command (from /tmp, TMPDIR=/tmp):", "",
+                 "```", cmds["valu"], "```", "",
+                 "Averages per dispatch.  VALU busy = SQ_ACTIVE_INST_VALU / SQ_BUSY_CU_CYCLES: one "
+                 "count per wave64 VALU instruction (4 cycles of a 16-lane SIMD) against CU cycles, "
+                 "4 SIMDs per CU.", "",
+                 "| kernel | kind | precision | VALU instr (wave) | VALU busy | LDS instr (wave) | "
+                 "LDS wait / wave-cycles |", "|---|---|---|---|---|---|---|"]
+        for name in sorted(per["SQ_INSTS_VALU"]):
+            c = classify_kernel(name)
+            if c is None or c[0] == "copy":
+                continue
+            avg = {n: (sum(per[n].get(name, [0])) / max(len(per[n].get(name, [])), 1)) for n in names}
+            busy = avg["SQ_ACTIVE_INST_VALU"] / max(avg["SQ_BUSY_CU_CYCLES"], 1)
+            ldsw = avg["SQ_WAIT_INST_LDS"] / max(avg["SQ_WAVE_CYCLES"], 1)
+            lines.append(f"| `{name.split('(')[0]}` | {c[0]} | {c[1] or '-'} | "
+                         f"{avg['SQ_INSTS_VALU']:.3g} | {busy:.2f} | {avg['SQ_INSTS_LDS']:.3g} | "
+                         f"{ldsw:.3f} |")
+        with open(os.path.join(prof_dir, f"valu_{wname}.md"), "w") as fh:
+            fh.write("\n".join(lines) + "\n")
     print(f"wrote profiles/kernel_trace_{wname}.md, profiles/hbm_traffic_{wname}.md, "
-          f"profiles/traffic.json")
+          f"profiles/traffic.json and (with valu/) profiles/valu_{wname}.md")
 
 
 def main():

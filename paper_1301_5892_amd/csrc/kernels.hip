@@ -97,6 +97,16 @@ __device__ __forceinline__ double expm1_t<double>(double x) { return expm1(x); }
 
 template <typename T>
 __device__ __forceinline__ T fma_t(T a, T b, T c) { return __builtin_fma(a, b, c); }
+
+// Device pointers known to address global memory: accesses through them
+// compile to global_* instructions (a 32-bit offset from a base, LDS
+// counters untouched) instead of flat ones.
+template <typename T>
+using gmem = __attribute__((address_space(1))) T;
+template <typename T>
+__device__ __forceinline__ gmem<T> *as_global(T *p) { return (gmem<T> *)p; }
+template <typename T>
+__device__ __forceinline__ const gmem<T> *as_global(const T *p) { return (const gmem<T> *)p; }
 template <>
 __device__ __forceinline__ float fma_t<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
@@ -114,7 +124,7 @@ template <typename T, int N, int R, int TPF>
 __device__ __forceinline__ void deltaf_source(const SimDev &S, double tauE, int p0,
                                               T (&src)[R]) {
     static_for<0, R>([&](auto kc) { src[decltype(kc)::value] = (T)0; });
-    const T *fg = (const T *)S.feq_g;
+    const gmem<T> *fg = as_global((const T *)S.feq_g);
     const T vmin = (T)S.vmin, dv = (T)S.dv;
     const int kw = (N - p0 + TPF - 1) / TPF;  // first wrapped k (R when none)
     const int pw = p0 + kw * TPF - N;         // its position
@@ -124,7 +134,7 @@ __device__ __forceinline__ void deltaf_source(const SimDev &S, double tauE, int 
         const T A = (T)A64;
         const T C = (T)(-A64 * S.feq_c[g] - 0.5 * tauE * tauE * is2);
         const T rm1 = expm1_t<T>((T)(A64 * (double)TPF * S.dv));
-        const T *row = fg + g * N;
+        const gmem<T> *row = fg + g * N;
         const T e0 = expm1_t<T>(fma_t<T>(A, vmin + (T)p0 * dv, C));
         const T ew = expm1_t<T>(fma_t<T>(A, vmin + (T)(kw < R ? pw : 0) * dv, C));
         T e = e0;
@@ -305,8 +315,8 @@ __global__ __launch_bounds__(256) void sweep_kernel(const Batch b) {
     const cx<T> *tw = (const cx<T> *)(KIND == 0 ? S.tw_v : S.tw_x);
     const cx<T> *eps = (const cx<T> *)(KIND == 0 ? S.eps_v : S.eps_x) + t * kEpsRow;
     T *data = (T *)(KIND == 0 ? S.f : S.g);
-    T *pA = data + (size_t)lineA * N;
-    T *pB = data + (size_t)lineB * N;
+    gmem<T> *pA = as_global(data + (size_t)lineA * N);
+    gmem<T> *pB = as_global(data + (size_t)lineB * N);
 
     // Shift of each line, FP64: v-sweep beta = -tau E_i / dv, x-sweep
     // beta = -v_j dt / dx.
