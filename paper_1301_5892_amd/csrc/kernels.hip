@@ -387,7 +387,15 @@ __global__ __launch_bounds__(256) void sweep_kernel(const Batch b) {
 template <typename T, int N>
 struct Fused {
     using F = Fft<T, N>;
-    static constexpr int TB = sizeof(T) == 4 ? (N >= 512 ? 1024 : 512) : (N >= 512 ? 512 : 256);
+    // Threads per block and the minimum waves per SIMD they are compiled
+    // for.  Short lines take small blocks (3 waves per SIMD for FP32, up to
+    // 168 VGPRs, no spills) while keeping 8 or more lines per tile (32 bytes
+    // or more of each row); longer lines need larger blocks for tiles that
+    // wide: 2048 points 512 threads (8 lines), 4096 points 1024 threads
+    // (8 lines, at most 128 VGPRs).  FP64: 256 threads up to 2048 points.
+    static constexpr int TB = sizeof(T) == 4 ? (N > 2048 ? 1024 : (N == 2048 ? 512 : 256))
+                                             : (N >= 4096 ? 512 : 256);
+    static constexpr int WAVES = sizeof(T) == 4 ? (N <= 1024 ? 3 : (N == 2048 ? 2 : 1)) : 2;
     static constexpr int PPB = TB / F::TPF;     // line pairs per block
     static constexpr int B = 2 * PPB;           // lines per block
     static constexpr int VEC = 16 / sizeof(T);  // elements per 16-byte vector
@@ -401,7 +409,7 @@ template <typename T, int N>
 constexpr int kFusedThreads = Fused<T, N>::TB;
 
 template <typename T, int N>
-__global__ __launch_bounds__((kFusedThreads<T, N>)) void xsweep_fused_kernel(const Batch b) {
+__global__ __launch_bounds__((kFusedThreads<T, N>), (Fused<T, N>::WAVES)) void xsweep_fused_kernel(const Batch b) {
     using F = Fft<T, N>;
     using C = Fused<T, N>;
     constexpr int R = F::R, TPF = F::TPF;
@@ -676,11 +684,22 @@ __global__ __launch_bounds__(kFieldThreads<N>) void field_kernel(const Batch b) 
         return x;
     };
 
+    const gmem<double> *rho = as_global(S.rho);
     cx<double> v[R];
     static_for<0, R>([&](auto rc) {
         constexpr int r = decltype(rc)::value;
-        v[r] = cx<double>{S.rho[t + r * TPF], 0.0};
+        v[r] = cx<double>{rho[t + r * TPF], 0.0};
     });
+    // 1/(N k_m) for this thread's modes, requested now so that the loads
+    // overlap the forward transform (Fourier solve only).
+    double ik[R];
+    if (S.poisson != VOG_POISSON_TRAPEZOID) {
+        const gmem<double> *invk = as_global(S.invk);
+        static_for<0, R>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            ik[k] = invk[t + TPF * k];
+        });
+    }
     F::template run<-1>(v, t, lre, lim, tab);
 
     // rho_hat_0 .. rho_hat_7 (unnormalised here).
@@ -700,12 +719,12 @@ __global__ __launch_bounds__(kFieldThreads<N>) void field_kernel(const Batch b) 
         // Contiguous chunk j = t R .. t R + R - 1 of rho~ = rho - mean and the
         // increments dx (rho~_j + rho~_{j+1}) / 2 for j < N - 1.
         double acc = 0.0, loc[R];
-        double rj = S.rho[t * R] - mean;
+        double rj = rho[t * R] - mean;
         static_for<0, R>([&](auto jc) {
             constexpr int jj = decltype(jc)::value;
             const int j = t * R + jj;
             loc[jj] = acc;  // sum of the chunk's increments before j
-            const double rn = (j + 1 < N) ? S.rho[j + 1] - mean : 0.0;
+            const double rn = (j + 1 < N) ? rho[j + 1] - mean : 0.0;
             if (j + 1 < N) acc += S.dx * 0.5 * (rj + rn);
             rj = rn;
         });
@@ -747,8 +766,7 @@ __global__ __launch_bounds__(kFieldThreads<N>) void field_kernel(const Batch b) 
         static_for<0, R>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
             constexpr int k = F::kpos(i);
-            const double ik = S.invk[t + TPF * k];
-            Y[k] = cx<double>{v[i].im * ik, -v[i].re * ik};
+            Y[k] = cx<double>{v[i].im * ik[k], -v[i].re * ik[k]};
         });
         F::template run<1>(Y, t, lre, lim, tab);
         static_for<0, R>([&](auto ic) {
@@ -764,8 +782,8 @@ __global__ __launch_bounds__(kFieldThreads<N>) void field_kernel(const Batch b) 
         constexpr int i = decltype(ic)::value;
         const int j = t + TPF * F::kpos(i);
         const double ej = S.field_zero ? 0.0 : e[i];
-        S.E[j] = ej;
-        S.Eeff[j] = damp == 0.0 ? ej : ej - damp * sin(S.drive_k * (j * S.dx) - dph);
+        as_global(S.E)[j] = ej;
+        as_global(S.Eeff)[j] = damp == 0.0 ? ej : ej - damp * sin(S.drive_k * (j * S.dx) - dph);
         e2 = fma(ej, ej, e2);
         finite = finite && isfinite(ej);
     });
