@@ -60,13 +60,36 @@ def test_named_workloads_validate(vog, w):
 @pytest.mark.parametrize("field,value", [
     ("nx", 12), ("nx", 4), ("nv", 8192), ("nv", 0), ("degree", 4), ("degree", 19),
     ("degree", 0), ("L", 0.0), ("L", float("nan")), ("vmax", -7.0), ("precision", 7),
-    ("poisson", 3), ("field", 2), ("n_feq", 0), ("n_feq", 5), ("moments_every", -1)])
+    ("poisson", 3), ("field", 2), ("n_feq", 0), ("n_feq", 5), ("moments_every", -1),
+    ("interp", 2), ("interp", -1), ("merge_v", 2), ("zero_mean", 3), ("precision", 4),
+    ("drive_emax", float("inf"))])
 def test_invalid_configs_rejected(vog, field, value):
     c = vog.make_config(workloads.landau_weak())
     setattr(c, field, value)
     assert vog.load().vog_config_validate(ctypes.byref(c)) == vog.EINVAL
     assert vog.workspace_bytes(c) == 0
     assert len(vog.load().vog_last_error()) > 0
+
+
+@pytest.mark.parametrize("precision", ["fp32_plain", "fp64_deltaf"])
+@pytest.mark.parametrize("interp", ["lagrange", "bspline"])
+def test_variant_configs_validate(vog, precision, interp):
+    w = workloads.landau_strong().replace(precision=precision, interp=interp, merge_v=True)
+    c = vog.make_config(w)
+    assert vog.load().vog_config_validate(ctypes.byref(c)) == 0
+    es = 4 if precision == "fp32_plain" else 8
+    nb = vog.workspace_bytes(c)
+    assert nb >= w.nx * w.nv * es
+    # B-splines add one table of 1/D_m per line length
+    base = vog.workspace_bytes(vog.make_config(w.replace(interp="lagrange")))
+    assert (nb > base) == (interp == "bspline")
+
+
+def test_drive_widths_must_be_positive(vog):
+    c = vog.make_config(workloads.keen(64))
+    assert vog.load().vog_config_validate(ctypes.byref(c)) == 0
+    c.drive_twl = 0.0
+    assert vog.load().vog_config_validate(ctypes.byref(c)) == vog.EINVAL
 
 
 def test_degree_must_fit_the_grid(vog):

@@ -293,3 +293,45 @@ def test_single_precision_study(gpu, capsys):
     assert t_df > t_fourier
     assert t_df > t_trap_zm
     assert t_trap < min(t_fourier, t_trap_zm)
+
+
+# ---------------------------------------------------------------- edge cases
+
+def test_zero_steps_is_a_no_op(gpu):
+    w = workloads.landau_strong()
+    s = gpu.Sim(w).init()
+    f0 = s.get_raw().copy()
+    s.diag()
+    s.step(0)
+    assert np.array_equal(s.get_raw(), f0)
+    assert s.diag().size == 0
+    assert s.time() == (0, 0.0)
+
+
+def test_batch_arguments_rejected(gpu):
+    import ctypes
+    from paper_1301_5892_amd import vog
+    L = vog.load()
+    s = gpu.Sim(workloads.landau_weak()).init()
+    dt = (ctypes.c_double * 2)(0.1, 0.1)
+    one = (ctypes.c_void_p * 1)(s.handle)
+    assert L.vog_step_batch(one, 0, dt, 1) == vog.EINVAL
+    two = (ctypes.c_void_p * 2)(s.handle, s.handle)
+    assert L.vog_step_batch(two, 2, dt, 1) == vog.EINVAL    # same sim twice
+    assert L.vog_step_batch(one, 1, dt, -1) == vog.EINVAL
+    bad = (ctypes.c_double * 1)(-0.1)
+    assert L.vog_step_batch(one, 1, bad, 1) == vog.EINVAL
+
+
+@pytest.mark.parametrize("interp,k", [("lagrange", 7), ("bspline", 7), ("bspline", 1)])
+@pytest.mark.parametrize("precision,tol", [("fp64_plain", TOL64), ("fp32_deltaf", TOL32)])
+def test_smallest_grid_runs(gpu, interp, k, precision, tol):
+    # 8 x 8, the smallest grid, with the widest stencil it allows.
+    w = workloads.landau_weak().replace(nx=8, nv=8, degree=k, interp=interp, precision=precision,
+                                         amp=(0.3,), kx=(0.5,), phase=(0.1,))
+    s = gpu.Sim(w).init()
+    o = oracle.Oracle(w).init()
+    s.step(5)
+    o.step(5)
+    got = s.get_raw() if precision == "fp32_deltaf" else s.get_f()
+    assert rel(got, o.f) < tol
