@@ -967,9 +967,13 @@ int vog_get_diag(vog_sim *s, vog_diag *out, int cap, int *n) {
     int64_t count = s->step - first + 1;
     if (count <= 0) return VOG_OK;
     if (count > cap) count = cap;
-    std::vector<vog_diag> ring(kRingCap);
-    HIP_TRY(hipMemcpy(ring.data(), s->host_dev.ring, sizeof(vog_diag) * kRingCap, hipMemcpyDeviceToHost));
-    for (int64_t k = 0; k < count; ++k) out[k] = ring[(first + k) % kRingCap];
+    // records first .. first+count-1 sit in at most two contiguous pieces of the ring
+    const int64_t head = first % kRingCap;
+    const int64_t n1 = std::min<int64_t>(count, kRingCap - head);
+    HIP_TRY(hipMemcpy(out, s->host_dev.ring + head, sizeof(vog_diag) * n1, hipMemcpyDeviceToHost));
+    if (count > n1)
+        HIP_TRY(hipMemcpy(out + n1, s->host_dev.ring, sizeof(vog_diag) * (count - n1),
+                          hipMemcpyDeviceToHost));
     *n = (int)count;
     s->diag_read = first + count;
     return VOG_OK;

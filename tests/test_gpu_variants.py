@@ -335,3 +335,20 @@ def test_smallest_grid_runs(gpu, interp, k, precision, tol):
     o.step(5)
     got = s.get_raw() if precision == "fp32_deltaf" else s.get_f()
     assert rel(got, o.f) < tol
+
+
+def test_diag_ring_wraps(gpu):
+    # Records are read in pieces that straddle the end of the 4096-record ring.
+    w = workloads.landau_weak().replace(nx=8, nv=8, degree=7)
+    s = gpu.Sim(w).init()
+    s.step(4090)
+    d0 = s.diag()
+    assert d0["step"][-1] == 4090 and np.all(np.diff(d0["step"]) == 1)
+    s.step(20)
+    d1 = s.diag()
+    assert list(d1["step"]) == list(range(4091, 4111))
+    assert np.all(d1["finite"] == 1)
+    ref = gpu.Sim(w).init()
+    ref.step(4110)
+    r = ref.diag()
+    assert np.array_equal(r["normE"][-20:], d1["normE"])
