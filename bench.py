@@ -45,6 +45,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=20)
     p.add_argument("--workload", default="large_grid")
     p.add_argument("--no-fp64", action="store_true")
+    p.add_argument("--no-merged", action="store_true",
+                   help="skip the merged-v-half-step FP32 leg")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--no-serving", action="store_true")
@@ -216,14 +218,14 @@ def cpu_baseline(w, seconds):
 # that scales FETCH_SIZE and WRITE_SIZE to bytes.
 PROFILE_COMMANDS = {
     "kt": "rocprofv3 --kernel-trace --stats -f csv -d {out}/kt -o kt -- python3 {root}/bench.py "
-          "--steps 100 --warmup 10 --no-serving --no-cpu-baseline --dram-sims 0 > {out}/kt.log",
+          "--steps 100 --warmup 10 --no-serving --no-cpu-baseline --dram-sims 0 --no-merged > {out}/kt.log",
     "fetch": "rocprofv3 --pmc FETCH_SIZE -f csv -d {out}/fetch -o fetch -- python3 {root}/bench.py "
-             "--steps 2 --warmup 1 --no-serving --no-cpu-baseline --dram-sims 0 --copy-calibration",
+             "--steps 2 --warmup 1 --no-serving --no-cpu-baseline --dram-sims 0 --no-merged --copy-calibration",
     "write": "rocprofv3 --pmc WRITE_SIZE -f csv -d {out}/write -o write -- python3 {root}/bench.py "
-             "--steps 2 --warmup 1 --no-serving --no-cpu-baseline --dram-sims 0 --copy-calibration",
+             "--steps 2 --warmup 1 --no-serving --no-cpu-baseline --dram-sims 0 --no-merged --copy-calibration",
     "valu": "rocprofv3 --pmc SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_BUSY_CU_CYCLES SQ_WAVE_CYCLES "
             "SQ_INSTS_LDS SQ_WAIT_INST_LDS -f csv -d {out}/valu -o valu -- python3 {root}/bench.py "
-            "--steps 2 --warmup 1 --no-serving --no-cpu-baseline --dram-sims 0 --copy-calibration",
+            "--steps 2 --warmup 1 --no-serving --no-cpu-baseline --dram-sims 0 --no-merged --copy-calibration",
 }
 COPY_CALIBRATION_BYTES = 256 << 20
 
@@ -479,6 +481,12 @@ def main():
                              "kernels_ms_per_step": {k: v[0] / K for k, v in prof64.items()},
                              "roofline": roofline_for(w, "fp64_plain", prof64, K)}
         out["fp32_over_fp64"] = out["value"] / out["fp64_plain"]["value"]
+    if not args.no_merged:
+        # Opt-in variant: v half-steps of consecutive steps merged (2 sweeps per
+        # step), all --steps steps in one call.  Not the headline scheme.
+        elm, _, finm, _ = run_gpu(w.replace(merge_v=True), "fp32_deltaf", K, W)
+        out["fp32_deltaf_merged_v"] = {"value": w.cells * K / elm, "ms_per_step": elm / K * 1e3,
+                                       "finite": finm}
     if args.dram_sims > 0:
         out["dram_batch"] = run_dram(w, args.dram_sims, K, W)
     if not args.no_serving:

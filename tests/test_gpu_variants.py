@@ -352,3 +352,26 @@ def test_diag_ring_wraps(gpu):
     ref.step(4110)
     r = ref.diag()
     assert np.array_equal(r["normE"][-20:], d1["normE"])
+
+
+def test_bump_on_tail_mass_error_ordering(gpu, capsys):
+    # Section 4.2 (bump on tail): the mass error |rho_hat_0(t) - rho_hat_0(0)|
+    # accumulates in time; in single precision the delta-f form keeps it
+    # smaller than plain f, and double precision is far below both.
+    w = workloads.bump_on_tail().replace(nsteps=2000)
+    err = {}
+    for precision in ("fp64_plain", "fp32_deltaf", "fp32_plain"):
+        s = gpu.Sim(w.replace(precision=precision)).init()
+        s.step(w.nsteps)
+        d = s.diag()
+        s.close()
+        assert np.all(d["finite"] == 1)
+        drift = np.abs(d["rho0"] - d["rho0"][0])
+        err[precision] = (float(np.max(drift[: w.nsteps // 4 + 1])), float(np.max(drift)))
+    with capsys.disabled():
+        print("\nbump-on-tail mass error (first quarter, whole run): " +
+              ", ".join(f"{k} {a:.2e} {b:.2e}" for k, (a, b) in err.items()))
+    assert err["fp64_plain"][1] < 1e-3 * err["fp32_deltaf"][1]
+    assert err["fp32_deltaf"][1] < err["fp32_plain"][1]
+    for k in ("fp32_deltaf", "fp32_plain"):
+        assert err[k][1] > err[k][0]          # it accumulates
