@@ -380,10 +380,12 @@ __global__ __launch_bounds__(256) void sweep_kernel(const Batch b) {
 
 // x-advection by dt = b.a[sim] directly on the v-fastest layout f[nx][nv]
 // (N = nx): a block owns the x-lines j0 .. j0 + B - 1, i.e. the tile
-// f[0..N)[j0..j0+B), staged through LDS with 16-byte row-segment loads and
-// stores, and runs the packed line-pair transform on B / 2 pairs at once.
-// Tiles are ordered so that the blocks sharing cache lines (neighbouring j0)
-// run on the same XCD at the same time.
+// f[0..N)[j0..j0+B), and runs the packed line-pair transform on B / 2 pairs
+// at once.  Loads go straight to registers: the B / 2 threads that share a
+// position t read the row's B contiguous values together.  The shifted
+// results are staged through LDS and stored as 16-byte row segments.  Tiles
+// are ordered so that the blocks sharing cache lines (neighbouring j0) run
+// on the same XCD at the same time.
 template <typename T, int N>
 struct Fused {
     using F = Fft<T, N>;
@@ -427,8 +429,10 @@ __global__ __launch_bounds__((kFusedThreads<T, N>), (Fused<T, N>::WAVES)) void x
     const int tid = threadIdx.x;
 
     // Shifts and weights first, while no tile data is live in registers.
-    const int slot = tid / TPF;
-    const int t = tid % TPF;
+    // Pairs are the fastest-varying part of the thread index, so the PPB
+    // threads with the same t read one row's 2 PPB contiguous values.
+    const int slot = tid % C::PPB;
+    const int t = tid / C::PPB;
     const int lineA = j0 + 2 * slot, lineB = lineA + 1;
     const double dt = b.a[blockIdx.y];
     long long bA, bB;
@@ -437,44 +441,23 @@ __global__ __launch_bounds__((kFusedThreads<T, N>), (Fused<T, N>::WAVES)) void x
     split_shift(-(S.vmin + lineB * S.dv) * dt * S.inv_dx, bB, sB);
     pair_weights<T, N, TPF>(S.d, S.interp, sA, sB, t, wsh[slot][0], wsh[slot][1]);
 
-    // Tile to LDS: column c of the tile is line j0 + c; pair c / 2 keeps line
-    // 2p in its real array and line 2p + 1 in its imaginary array.
-    static_for<0, C::ITER>([&](auto kc) {
-        constexpr int k = decltype(kc)::value;
-        const int q = tid + k * C::TB;
-        const int row = q / C::VPR, cv = q % C::VPR;
-        const T *src = f + (size_t)row * nv + j0 + cv * C::VEC;
-        T e[C::VEC];
-        if constexpr (sizeof(T) == 4) {
-            const float4 x = *reinterpret_cast<const float4 *>(src);
-            e[0] = x.x; e[1] = x.y; e[2] = x.z; e[3] = x.w;
-        } else {
-            const double2 x = *reinterpret_cast<const double2 *>(src);
-            e[0] = x.x; e[1] = x.y;
-        }
-        const int pr = F::pad(row);
-        static_for<0, C::VEC>([&](auto ec) {
-            constexpr int el = decltype(ec)::value;
-            const int c = cv * C::VEC + el;  // (c / 2) * 2 + c % 2 == c
-            lds[c * C::LDSP + pr] = e[el];
+    // The pair's two lines straight into registers: v[r] = z[t + r TPF],
+    // z = u_lineA + i u_lineB, one 2-value load per row.
+    cx<T> v[R];
+    {
+        typedef T v2t __attribute__((ext_vector_type(2)));
+        const gmem<v2t> *src = (const gmem<v2t> *)(f + (size_t)t * nv + lineA);
+        static_for<0, R>([&](auto rc) {
+            constexpr int r = decltype(rc)::value;
+            const v2t z = src[(size_t)r * TPF * (nv / 2)];
+            v[r] = cx<T>{z.x, z.y};
         });
-    });
+    }
 
     T *lre = lds + (2 * slot) * C::LDSP;
     T *lim = lre + C::LDSP;
     const cx<T> *tw = (const cx<T> *)S.tw_x;
     const cx<T> *eps = (const cx<T> *)S.eps_x + t * kEpsRow;
-
-    __syncthreads();  // tile and weights in LDS
-    cx<T> v[R];
-    {
-        const int pt = F::pad(t);
-        static_for<0, R>([&](auto rc) {
-            constexpr int r = decltype(rc)::value;
-            const int idx = F::template pad_add<r * TPF>(pt);
-            v[r] = cx<T>{lre[idx], lim[idx]};
-        });
-    }
 
     cx<T> Y[R];
     pair_transform<T, N, true>(v, Y, t, lre, lim, tw, eps, wsh[slot][0], wsh[slot][1],
