@@ -296,14 +296,14 @@ def summarize_rocprof(folder, wname):
     and profiles/traffic.json from the output of PROFILE_COMMANDS."""
     prof_dir = os.path.join(ROOT, "profiles")
     os.makedirs(prof_dir, exist_ok=True)
-    cmds = {k: v.format(out="/root/repo/gpurun_out/prof", root="/root/repo")
-            for k, v in PROFILE_COMMANDS.items()}
+    cmds = {k: v.format(out="$OUT", root="$REPO") for k, v in PROFILE_COMMANDS.items()}
     bench_rec = _last_json(os.path.join(folder, "kt.log"))
 
     # kernel trace statistics
     stats = _csv_rows(os.path.join(folder, "kt"), "kernel_stats.csv")
     lines = [f"# Kernel trace, {wname}", "",
-             "Command (from /tmp, TMPDIR=/tmp):", "", "```", cmds["kt"], "```", "",
+             "Command (from /tmp, TMPDIR=/tmp; $REPO is the repository root, $OUT the output "
+             "folder):", "", "```", cmds["kt"], "```", "",
              "| kernel | kind | precision | calls | avg us | min us | max us | % time |",
              "|---|---|---|---|---|---|---|---|"]
     trace_avg = {}
@@ -347,7 +347,8 @@ def summarize_rocprof(folder, wname):
         with open(table_path) as fh:
             table = json.load(fh)
     lines = [f"# HBM traffic per launch, {wname}", "",
-             "Commands (from /tmp, TMPDIR=/tmp):", "", "```", cmds["fetch"], cmds["write"], "```", "",
+             "Commands (from /tmp, TMPDIR=/tmp; $REPO is the repository root, $OUT the output "
+             "folder):", "", "```", cmds["fetch"], cmds["write"], "```", "",
              f"Calibration: one {COPY_CALIBRATION_BYTES >> 20} MiB device-to-device copy "
              f"(`__amd_rocclr_copyBuffer`) reads FETCH_SIZE = {copy_f:.0f} KiB and "
              f"WRITE_SIZE = {copy_w:.0f} KiB against {cal_kib:.0f} KiB moved each way, so the "
@@ -394,7 +395,9 @@ def summarize_rocprof(folder, wname):
         names = ("SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU", "SQ_BUSY_CU_CYCLES", "SQ_WAVE_CYCLES",
                  "SQ_INSTS_LDS", "SQ_WAIT_INST_LDS")
         per = {n: _counter_per_kernel(vdir, n) for n in names}
-        lines = [f"# VALU issue per kernel, {wname}", "", "Command (from /tmp, TMPDIR=/tmp):", "",
+        lines = [f"# VALU issue per kernel, {wname}", "",
+                 "Command (from /tmp, TMPDIR=/tmp; $REPO is the repository root, $OUT the output "
+                 "folder):", "",
                  "```", cmds["valu"], "```", "",
                  "Averages per dispatch.  VALU busy = SQ_ACTIVE_INST_VALU / SQ_BUSY_CU_CYCLES: one "
                  "count per wave64 VALU instruction (4 cycles of a 16-lane SIMD) against CU cycles, "
@@ -424,8 +427,8 @@ def main():
         summarize_rocprof(args.summarize_rocprof, getattr(workloads, args.workload)().name)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); "
-              f"independent simulations shard one per GPU, see DESIGN.md", file=sys.stderr)
+        print(f"bench.py measures one GPU (got --gpus {args.gpus}): a simulation runs on one "
+              f"GPU, and independent simulations shard one per GPU", file=sys.stderr)
         sys.exit(2)
     import torch
     import workloads
