@@ -460,8 +460,10 @@ __global__ __launch_bounds__((kFusedThreads<T, N>), (Fused<T, N>::WAVES)) void x
     const cx<T> *eps = (const cx<T> *)S.eps_x + t * kEpsRow;
 
     cx<T> Y[R];
-    pair_transform<T, N, true>(v, Y, t, lre, lim, tw, eps, wsh[slot][0], wsh[slot][1],
-                               (const T *)S.iden_x);
+    // FP32 lines up to 512 points keep the twiddle rows in registers (measured
+    // faster there); longer lines and FP64 re-read them to stay unspilled.
+    pair_transform<T, N, !(sizeof(T) == 4 && N <= 512)>(v, Y, t, lre, lim, tw, eps, wsh[slot][0],
+                                                         wsh[slot][1], (const T *)S.iden_x);
 
     // Shifted result back to LDS: unshifted index j goes to position (j - b) mod N.
     __syncthreads();
