@@ -478,3 +478,18 @@ def test_merged_landau_rate(orc):
     gamma, omega, _ = orc.landau_fit(t, d[:, 0])
     assert abs(-gamma - _paper()["gamma"]) / _paper()["gamma"] < 0.05
     assert abs(omega - 1.4156) / 1.4156 < 0.01
+
+
+def test_fp32_rounding_sensitivity_is_far_below_the_gate(orc):
+    # The FP32 delta-f gate (1e-5 relative) must sit above what FP32 storage
+    # alone causes: rounding delta f0 to FP32 and running 10 strong-Landau steps
+    # in FP64 moves delta f by a few FP32 ulps, not more.
+    w = workloads.landau_strong()
+    a = orc.Oracle(w).init()
+    b = orc.Oracle(w).init()
+    b.f = b.f.astype(np.float32).astype(np.float64)
+    b.update_field()
+    a.step(10)
+    b.step(10)
+    d = np.max(np.abs(a.f - b.f)) / np.max(np.abs(a.f))
+    assert 0.0 < d < 1e-6
