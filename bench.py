@@ -45,6 +45,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=20)
     p.add_argument("--workload", default="large_grid")
     p.add_argument("--no-fp64", action="store_true")
+    p.add_argument("--no-keen", action="store_true",
+                   help="skip the KEEN 4096x4096 leg (the paper's timed workload)")
     p.add_argument("--no-merged", action="store_true",
                    help="skip the merged-v-half-step FP32 leg")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -218,14 +220,14 @@ def cpu_baseline(w, seconds):
 # that scales FETCH_SIZE and WRITE_SIZE to bytes.
 PROFILE_COMMANDS = {
     "kt": "rocprofv3 --kernel-trace --stats -f csv -d {out}/kt -o kt -- python3 {root}/bench.py "
-          "--steps 100 --warmup 10 --no-serving --no-cpu-baseline --dram-sims 0 --no-merged > {out}/kt.log",
+          "--steps 100 --warmup 10 --no-serving --no-cpu-baseline --dram-sims 0 --no-merged --no-keen > {out}/kt.log",
     "fetch": "rocprofv3 --pmc FETCH_SIZE -f csv -d {out}/fetch -o fetch -- python3 {root}/bench.py "
-             "--steps 2 --warmup 1 --no-serving --no-cpu-baseline --dram-sims 0 --no-merged --copy-calibration",
+             "--steps 2 --warmup 1 --no-serving --no-cpu-baseline --dram-sims 0 --no-merged --no-keen --copy-calibration",
     "write": "rocprofv3 --pmc WRITE_SIZE -f csv -d {out}/write -o write -- python3 {root}/bench.py "
-             "--steps 2 --warmup 1 --no-serving --no-cpu-baseline --dram-sims 0 --no-merged --copy-calibration",
+             "--steps 2 --warmup 1 --no-serving --no-cpu-baseline --dram-sims 0 --no-merged --no-keen --copy-calibration",
     "valu": "rocprofv3 --pmc SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_BUSY_CU_CYCLES SQ_WAVE_CYCLES "
             "SQ_INSTS_LDS SQ_WAIT_INST_LDS -f csv -d {out}/valu -o valu -- python3 {root}/bench.py "
-            "--steps 2 --warmup 1 --no-serving --no-cpu-baseline --dram-sims 0 --no-merged --copy-calibration",
+            "--steps 2 --warmup 1 --no-serving --no-cpu-baseline --dram-sims 0 --no-merged --no-keen --copy-calibration",
 }
 COPY_CALIBRATION_BYTES = 256 << 20
 
@@ -484,6 +486,15 @@ def main():
                              "kernels_ms_per_step": {k: v[0] / K for k, v in prof64.items()},
                              "roofline": roofline_for(w, "fp64_plain", prof64, K)}
         out["fp32_over_fp64"] = out["value"] / out["fp64_plain"]["value"]
+    if not args.no_keen:
+        # The paper's timed workload (Section 4.3, Table 1): KEEN waves at
+        # N = 4096, FP32 delta f, drive on; its C2070 figure is quoted as is.
+        wk = workloads.keen(4096, 0.05, K)
+        elk, _, fink, _ = run_gpu(wk, "fp32_deltaf", K, W)
+        out["keen_4096"] = {"value": wk.cells * K / elk, "unit": "cell-updates/s",
+                            "ms_per_step": elk / K * 1e3, "finite": fink,
+                            "paper_c2070": 2.047e8,
+                            "vs_paper_c2070": wk.cells * K / elk / 2.047e8}
     if not args.no_merged:
         # Opt-in variant: v half-steps of consecutive steps merged (2 sweeps per
         # step), all --steps steps in one call.  Not the headline scheme.
