@@ -131,7 +131,7 @@ int vog_config_validate(const vog_config *cfg);
 
 /* Exact number of device bytes a sim of this configuration uses (f, a
  * transposed scratch copy when the x-sweep cannot run on the v-fastest
- * layout (nx < 256 or nv smaller than one tile of x-lines), field, partial
+ * layout (nx < 64 or nv smaller than one tile of x-lines), field, partial
  * sums, tables, diagnostics ring).  Returns 0 for an invalid configuration. */
 size_t vog_workspace_bytes(const vog_config *cfg);
 

@@ -507,23 +507,27 @@ static void launch_xsweep_fused(const Batch &b, int max_lines, hipStream_t st) {
 
 template <typename T, int... L>
 static LaunchFn pick_fused(int logn, std::integer_sequence<int, L...>) {
-    LaunchFn fns[] = {&launch_xsweep_fused<T, (256 << L)>...};
-    return fns[logn - 8];
+    LaunchFn fns[] = {&launch_xsweep_fused<T, (64 << L)>...};
+    return fns[logn - 6];
 }
 
+// Lines per tile of the x-sweep on the v-fastest layout for x-lines of nx
+// points (64 .. 4096), 0 where it does not apply.
 int fused_lines_per_block(bool fp64, int nx) {
     const int logn = ilog2(nx);
-    if (nx < 256 || nx > VOG_MAX_N || (1 << logn) != nx) return 0;
-    constexpr int tf[5] = {Fused<float, 256>::B, Fused<float, 512>::B, Fused<float, 1024>::B,
-                           Fused<float, 2048>::B, Fused<float, 4096>::B};
-    constexpr int td[5] = {Fused<double, 256>::B, Fused<double, 512>::B, Fused<double, 1024>::B,
-                           Fused<double, 2048>::B, Fused<double, 4096>::B};
-    return fp64 ? td[logn - 8] : tf[logn - 8];
+    if (nx < 64 || nx > VOG_MAX_N || (1 << logn) != nx) return 0;
+    constexpr int tf[7] = {Fused<float, 64>::B, Fused<float, 128>::B, Fused<float, 256>::B,
+                           Fused<float, 512>::B, Fused<float, 1024>::B, Fused<float, 2048>::B,
+                           Fused<float, 4096>::B};
+    constexpr int td[7] = {Fused<double, 64>::B, Fused<double, 128>::B, Fused<double, 256>::B,
+                           Fused<double, 512>::B, Fused<double, 1024>::B, Fused<double, 2048>::B,
+                           Fused<double, 4096>::B};
+    return fp64 ? td[logn - 6] : tf[logn - 6];
 }
 
 LaunchFn fused_xsweep_launcher(bool fp64, int nx) {
     if (fused_lines_per_block(fp64, nx) == 0) return nullptr;
-    using Seq = std::make_integer_sequence<int, 5>;
+    using Seq = std::make_integer_sequence<int, 7>;
     return fp64 ? pick_fused<double>(ilog2(nx), Seq{}) : pick_fused<float>(ilog2(nx), Seq{});
 }
 
