@@ -146,7 +146,7 @@ class Scheduler:
 class GpuExecutor:
     """Runs requests with libvog on the current torch stream."""
 
-    def __init__(self, moments_every: int = 0, keep_state: bool = False):
+    def __init__(self, moments_every: int = 0, keep_state: bool = False, digest: bool = False):
         import torch
 
         from . import vog
@@ -154,6 +154,7 @@ class GpuExecutor:
         self.vog = vog
         self.moments_every = moments_every
         self.keep_state = keep_state
+        self.digest = digest
         vog.load()
 
     def now(self) -> float:
@@ -188,12 +189,15 @@ class GpuExecutor:
             raise
 
     def finish(self, h):
-        raw = h.get_raw()
-        E = h.get_E()
-        out = {"E": E, "digest": hashlib.sha256(raw.tobytes()).hexdigest(),
-               "step": h.time()[0]}
-        if self.keep_state:
-            out["raw"] = raw
+        """Result of a finished request: the final field and step count; the
+        stored f (keep_state) and its SHA-256 (digest) on request."""
+        out = {"E": h.get_E(), "step": h.time()[0]}
+        if self.keep_state or self.digest:
+            raw = h.get_raw()
+            if self.digest:
+                out["digest"] = hashlib.sha256(raw.tobytes()).hexdigest()
+            if self.keep_state:
+                out["raw"] = raw
         return out
 
     def release(self, h) -> None:
