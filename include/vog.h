@@ -60,7 +60,7 @@ extern "C" {
 #define VOG_FIELD_ZERO            1  /* E held at zero: free streaming */
 
 #define VOG_MAX_FEQ    4
-#define VOG_MAX_DEGREE 17   /* Lagrange 2d+1 with d <= 8 (LAG17, Section 4) */
+#define VOG_MAX_DEGREE 17   /* odd degree 2d+1 with d <= 8: LAG17 (Section 4), B-splines up to degree 17 */
 #define VOG_MIN_N      8
 #define VOG_MAX_N      4096
 
@@ -176,11 +176,12 @@ int vog_set_E(vog_sim *sim, const double *host_E);
 /* Enqueues nsteps Strang steps of size dt (Section 1.1):
  *   v-advection by dt/2 with E^n, x-advection by dt, field update
  *   E^{n+1} from rho = int f dv, v-advection by dt/2 with E^{n+1};
- * the last half step is not merged with the next step's first.  Each
- * constant advection is the circulant product A u of Section 1.2 with
- * Lagrange 2d+1 coefficients, applied as FFT -> multiply by the diagonal of
- * A in Fourier space -> inverse FFT.  Asynchronous: returns after enqueueing.
- * dt > 0 and finite, nsteps >= 0. */
+ * the last half step is not merged with the next step's first unless the
+ * configuration sets merge_v.  Each constant advection is the circulant
+ * product A u of Section 1.2 (Lagrange 2d+1 or B-spline coefficients),
+ * applied as FFT -> multiply by the diagonal of A in Fourier space ->
+ * inverse FFT.  With a drive, the v-advections use E - E_app.  Asynchronous:
+ * returns after enqueueing.  dt > 0 and finite, nsteps >= 0 (0: no-op). */
 int vog_step(vog_sim *sim, double dt, int nsteps);
 
 /* nsteps Strang steps for nsims sims at once, sim k with step dt[k], with one
