@@ -229,6 +229,25 @@ def test_free_streaming(gpu, precision):
     assert np.max(np.abs(s.get_E())) == 0.0
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64_plain", TOL64), ("fp32_deltaf", TOL32)])
+def test_free_streaming_full_size(gpu, precision, tol):
+    # The 4096 x 4096 large-grid data with the field off, against the exact
+    # solution f0(x - v t, v) evaluated on every cell (a property that holds
+    # at any size, here in the launch configuration the benchmark times).
+    w = workloads.large_grid().replace(field="zero", precision=precision, nsteps=10)
+    s = sim_of(gpu, w).init()
+    s.step(w.nsteps)
+    x = (np.arange(w.nx) * w.L / w.nx)[:, None]
+    v = (w.vmin + np.arange(w.nv) * (w.vmax - w.vmin) / w.nv)[None, :]
+    t = w.nsteps * w.dt
+    pert = sum(a * np.cos(k * (x - v * t) + ph) for a, k, ph in zip(w.amp, w.kx, w.phase))
+    fm = np.exp(-v ** 2 / 2) / math.sqrt(2 * math.pi)
+    if precision == "fp32_deltaf":
+        assert rel(s.get_raw(), pert * fm) < tol
+    else:
+        assert rel(s.get_f(), (1 + pert) * fm) < tol
+
+
 def test_landau_fp64_deltaf_matches_oracle(gpu):
     w = workloads.landau_weak().replace(precision="fp64_deltaf")
     s = sim_of(gpu, w).init()
