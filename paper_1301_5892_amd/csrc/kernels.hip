@@ -397,7 +397,8 @@ struct Fused {
     // (8 lines, at most 128 VGPRs).  FP64: 256 threads up to 2048 points.
     static constexpr int TB = sizeof(T) == 4 ? (N > 2048 ? 1024 : (N == 2048 ? 512 : 256))
                                              : (N >= 4096 ? 512 : 256);
-    static constexpr int WAVES = sizeof(T) == 4 ? (N <= 1024 ? 3 : (N == 2048 ? 2 : 1)) : 2;
+    static constexpr int WAVES = sizeof(T) == 4 ? (N <= 1024 ? 3 : (N == 2048 ? 2 : 1))
+                                                : (N >= 256 ? 2 : 1);  // short FP64 lines: LDS-bound
     static constexpr int PPB = TB / F::TPF;     // line pairs per block
     static constexpr int B = 2 * PPB;           // lines per block
     static constexpr int VEC = 16 / sizeof(T);  // elements per 16-byte vector
@@ -572,14 +573,17 @@ __global__ __launch_bounds__(256) void transpose_kernel(const Batch b) {
     if (tr >= tilesR) return;
     const int r0 = tr * kTile, c0 = tc * kTile;
     const int tx = threadIdx.x & (kTile - 1), ty = threadIdx.x / kTile;
+    constexpr int kRows = 256 / kTile;  // tile rows handled per pass of the block
 #pragma unroll
-    for (int rr = ty; rr < kTile; rr += 256 / kTile) {
+    for (int i = 0; i < kTile / kRows; ++i) {
+        const int rr = ty + i * kRows;
         const int r = r0 + rr, c = c0 + tx;
         if (r < rows && c < cols) tile[rr][tx] = in[(size_t)r * cols + c];
     }
     __syncthreads();
 #pragma unroll
-    for (int cc = ty; cc < kTile; cc += 256 / kTile) {
+    for (int i = 0; i < kTile / kRows; ++i) {
+        const int cc = ty + i * kRows;
         const int c = c0 + cc, r = r0 + tx;
         if (r < rows && c < cols) out[(size_t)c * rows + r] = tile[tx][cc];
     }
