@@ -241,7 +241,6 @@ void orc_init(const orc_cfg *c, int nmodes, const double *amp, const double *kx,
     }
 }
 
-/* x-advection by dt (Section 1.1, step 2): for each v_j, c = v_j. */
 /* Lines of one sweep: nl lines of length n, line l starting at base + l ls
  * with element stride es; beta(l) gives the normalized shift of line l. */
 typedef double (*beta_fn)(const orc_cfg *c, const double *E, double arg, int l);
@@ -288,10 +287,16 @@ static void advect_lines(const orc_cfg *c, int n, int nl, long ls, long es, beta
     free(piv);
 }
 
+/* x-advection by dt (Section 1.1, step 2): line j (fixed v_j) is advected
+ * with speed v_j, beta = -v_j dt / dx. */
 void orc_advect_x(const orc_cfg *c, double dt, const double *f, double *out) {
     advect_lines(c, c->nx, c->nv, 1, c->nv, beta_x, NULL, dt, f, out);
 }
 
+/* v-advection by tau with field E (Section 1.1, steps 1 and 3): line i (fixed
+ * x_i) is advected with speed E_i, beta = -E_i tau / dv.  delta f form
+ * (Section 3.1): the advected perturbation plus f_eq(v - tau E_i) - f_eq(v),
+ * f_eq evaluated. */
 void orc_advect_v(const orc_cfg *c, const double *E, double tau, const double *f, double *out) {
     advect_lines(c, c->nv, c->nx, c->nv, 1, beta_v, E, tau, f, out);
     if (c->deltaf) {
@@ -307,6 +312,8 @@ void orc_advect_v(const orc_cfg *c, const double *E, double tau, const double *f
     }
 }
 
+/* rho_i = dv sum_j f_ij, the velocity integral by the rectangle rule on the
+ * periodic grid; in delta f form dv sum_j (delta f_ij + f_eq(v_j)). */
 void orc_rho(const orc_cfg *c, const double *f, double *rho) {
     const double dv = dv_of(c);
     double feq_sum = 0.0;
