@@ -2,16 +2,21 @@
 //
 //  sweep_kernel     one constant advection (Section 1.2) for a batch of lines:
 //                   forward FFT of two real lines packed as one complex line,
-//                   multiply by the diagonal of the circulant in Fourier space,
-//                   inverse FFT, integer part of the shift applied as an exact
-//                   cyclic index offset on the store, delta-f source term
-//                   (Section 3.1) on v-sweeps.
+//                   multiply by the diagonal of the circulant in Fourier space
+//                   (Lagrange or B-spline symbol), inverse FFT, integer part of
+//                   the shift applied as an exact cyclic index offset on the
+//                   store, delta-f source term (Section 3.1) on v-sweeps.
+//  xsweep_fused_kernel
+//                   the x-advection on the v-fastest layout, tiles of whole
+//                   x-lines loaded straight into registers.
 //  transpose_kernel tiled LDS transpose between the v-fastest and x-fastest
-//                   layouts; the x->v direction also emits FP64 partial sums
-//                   of f over 64 velocities for rho = int f dv.
-//  field_kernel     FP64 rho, FFT Poisson solve with mode 0 set to zero
-//                   (Section 3.2), E, and the per-step diagnostics record.
-//  rho_v_kernel, moments kernels, init and fill helpers.
+//                   layouts for grids the tiled x-sweep does not cover; the
+//                   x->v direction also emits FP64 partial sums of f over 64
+//                   velocities for rho = int f dv.
+//  field_kernel     FFT (or trapezoidal) Poisson solve in FP64 (Section 3.2),
+//                   E and E - E_app, and the per-step diagnostics record.
+//  rho_v_kernel     rho = int f dv from the v-fastest layout; moments
+//                   kernels, init and fill helpers.
 #include "fft.hpp"
 #include "vog_internal.hpp"
 
