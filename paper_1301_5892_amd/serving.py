@@ -54,9 +54,13 @@ class _Active:
 class Scheduler:
     """Admission by memory footprint + quantum-based continuous batching."""
 
-    def __init__(self, executor, budget_bytes: int, max_active: int = 64, quantum: int = 50):
-        if budget_bytes <= 0 or max_active <= 0 or quantum <= 0:
-            raise ValueError("budget, max_active and quantum must be positive")
+    def __init__(self, executor, budget_bytes: int, max_active: int = 64, quantum: int = 50,
+                 check_every: int = 4):
+        if budget_bytes <= 0 or max_active <= 0 or quantum <= 0 or check_every <= 0:
+            raise ValueError("budget, max_active, quantum and check_every must be positive")
+        # a simulation's field is checked for non-finite values every
+        # check_every quanta and when it completes (each check synchronises)
+        self.check_every = int(check_every)
         self.ex = executor
         self.budget = int(budget_bytes)
         self.max_active = int(max_active)
@@ -118,6 +122,7 @@ class Scheduler:
             counts = [min(self.quantum, a.remaining) for a in active]
             self.ex.advance([a.handle for a in active], counts)
             self.stats["quanta"] += 1
+            check = self.stats["quanta"] % self.check_every == 0
             tq = now()
             still: List[_Active] = []
             for a, c in zip(active, counts):
@@ -126,7 +131,7 @@ class Scheduler:
                 w = a.req.workload
                 if rid in self.cancelled:
                     status = "cancelled"
-                elif self.ex.failed(a.handle):
+                elif (a.remaining == 0 or check) and self.ex.failed(a.handle):
                     status = "failed"
                 elif a.remaining == 0:
                     status = "done"
