@@ -235,7 +235,7 @@ def summarize(outcomes: Sequence[Outcome]) -> Dict[str, Any]:
     }
 
 
-def bench(n_requests: int = 512, load_factor: float = 0.8, quantum: int = 50,
+def bench(n_requests: int = 512, load_factor: float = 0.8, quantum: int = 25,
           max_active: int = 128, budget_bytes: int = 64 << 30, seed: int = 1) -> Dict[str, Any]:
     """Serving mix: closed-loop capacity pass (all requests present at t=0),
     then an open-loop pass with Poisson arrivals at load_factor x capacity."""
