@@ -248,6 +248,51 @@ struct Fft {
             if constexpr (p + 1 < NPASS) exchange<p>(v, t, lre, lim);
         });
     }
+
+    // The twiddles every pass of thread t uses, held in registers: pass p
+    // (p >= 1) group u takes row (t + u TPF) mod NS(p), entries 0 .. RP-1, at
+    // w[p - 1][u RP ..].  The same rows serve both directions (forward
+    // passes multiply by their conjugates).  For kernels that run few blocks,
+    // where a table load inside each pass would be waited for in full.
+    struct Rows {
+        cx<T> w[NPASS > 1 ? NPASS - 1 : 1][R];
+    };
+    static __device__ __forceinline__ void load_rows(int t, const cx<T> *__restrict__ tw, Rows &rw) {
+        static_for<1, NPASS>([&](auto pc) {
+            constexpr int p = decltype(pc)::value;
+            constexpr int RP = radix(p), NS = ns(p);
+            static_for<0, R / RP>([&](auto uc) {
+                constexpr int u = decltype(uc)::value;
+                const int k = (t + u * TPF) & (NS - 1);
+                cx<T> w[RP];
+                load_row<T, RP>(tw + fft_tw_off(N, p) + 16 * k, w);
+                static_for<0, RP>([&](auto rc) {
+                    constexpr int r = decltype(rc)::value;
+                    rw.w[p - 1][u * RP + r] = w[r];
+                });
+            });
+        });
+    }
+    template <int DIR>
+    static __device__ __forceinline__ void run(cx<T> (&v)[R], int t, T *lre, T *lim, const Rows &rw) {
+        static_for<0, NPASS>([&](auto pc) {
+            constexpr int p = decltype(pc)::value;
+            constexpr int RP = radix(p);
+            static_for<0, R / RP>([&](auto uc) {
+                constexpr int u = decltype(uc)::value;
+                if constexpr (p > 0) {
+                    static_for<1, RP>([&](auto rc) {
+                        constexpr int r = decltype(rc)::value;
+                        const cx<T> w = rw.w[p - 1][u * RP + r];
+                        if constexpr (DIR > 0) v[u * RP + r] = cmul(v[u * RP + r], w);
+                        else v[u * RP + r] = cmul_conj(v[u * RP + r], w);
+                    });
+                }
+                dft<T, DIR, RP>(&v[u * RP]);
+            });
+            if constexpr (p + 1 < NPASS) exchange<p>(v, t, lre, lim);
+        });
+    }
 };
 
 }  // namespace vog

@@ -296,18 +296,26 @@ __device__ __forceinline__ void pair_transform(cx<T> (&v)[R], cx<T> (&Y)[R], int
 // or B-spline taps followed by the division by the collocation symbol).
 // The kernel is applied in Fourier space through its symbol and the shift by
 // b is applied exactly on the store (index j -> j - b mod N).
-template <typename T, int N, int KIND>
-__global__ __launch_bounds__(256) void sweep_kernel(const Batch b) {
+template <typename T, int N>
+struct Sweep {
     using F = Fft<T, N>;
-    constexpr int R = F::R, TPF = F::TPF, PPB = 256 / TPF;
-    __shared__ T lds[PPB][2][F::LDSN];
-    __shared__ T wsh[PPB][2][kTaps];
+    static constexpr int PPB = 256 / F::TPF;  // line pairs per 256-thread block
+    // LDS: the pairs' exchange arrays, then their weights
+    static constexpr int SMEM = PPB * 2 * F::LDSN + PPB * 2 * kTaps;
+};
 
-    const SimDev &S = *b.s[blockIdx.y];
+// Block blk of sim `sim` of the batch; smem holds Sweep<T, N>::SMEM values.
+template <typename T, int N, int KIND>
+__device__ __forceinline__ void sweep_body(const Batch &b, int sim, int blk, T *smem) {
+    using F = Fft<T, N>;
+    constexpr int R = F::R, TPF = F::TPF, PPB = Sweep<T, N>::PPB;
+    T(*lds)[2][F::LDSN] = reinterpret_cast<T(*)[2][F::LDSN]>(smem);
+    T(*wsh)[2][kTaps] = reinterpret_cast<T(*)[2][kTaps]>(smem + PPB * 2 * F::LDSN);
+
+    const SimDev &S = *b.s[sim];
     const int nlines = KIND == 0 ? S.nx : S.nv;
     const int npairs = nlines >> 1;
-    if ((int)blockIdx.x * PPB >= npairs) return;  // whole block idle
-    const int blk = (int)blockIdx.x;
+    if (blk * PPB >= npairs) return;  // whole block idle
 
     const int slot = threadIdx.x / TPF;
     const int t = threadIdx.x % TPF;
@@ -325,7 +333,7 @@ __global__ __launch_bounds__(256) void sweep_kernel(const Batch b) {
 
     // Shift of each line, FP64: v-sweep beta = -tau E_i / dv, x-sweep
     // beta = -v_j dt / dx.
-    const double arg = b.a[blockIdx.y];
+    const double arg = b.a[sim];
     double EA = 0.0, EB = 0.0, betaA, betaB;
     if constexpr (KIND == 0) {
         EA = S.Eeff[lineA];
@@ -383,6 +391,40 @@ __global__ __launch_bounds__(256) void sweep_kernel(const Batch b) {
     });
 }
 
+// One line length per launch: blockIdx.y = sim, blockIdx.x = block.
+template <typename T, int N, int KIND>
+__global__ __launch_bounds__(256, (sizeof(T) == 4 && N >= 32 ? 3 : 1)) void sweep_kernel(const Batch b) {
+    __shared__ T smem[Sweep<T, N>::SMEM];
+    sweep_body<T, N, KIND>(b, (int)blockIdx.y, (int)blockIdx.x, smem);
+}
+
+// Sim of block bid in a launch over mixed line lengths (m.first ascending).
+__device__ __forceinline__ int mixed_sim(const Batch &b, const BlockMap &m, int bid) {
+    int k = 0;
+    while (k + 1 < b.n && m.first[k + 1] <= bid) ++k;
+    return k;
+}
+
+// FP32 v-sweeps of sims with lines of 64 .. 4096 points in one launch: every
+// block runs the body of its sim's line length (each block carries 8192
+// values whatever the length).
+__global__ __launch_bounds__(256, 3) void sweep_v_mixed_kernel(const Batch b, const BlockMap m) {
+    __shared__ float smem[Sweep<float, 64>::SMEM];  // the largest of 64 .. 4096
+    const int bid = (int)blockIdx.x;
+    const int k = mixed_sim(b, m, bid);
+    const int blk = bid - m.first[k];
+    switch (m.lgn[k]) {
+    case 6: sweep_body<float, 64, 0>(b, k, blk, smem); break;
+    case 7: sweep_body<float, 128, 0>(b, k, blk, smem); break;
+    case 8: sweep_body<float, 256, 0>(b, k, blk, smem); break;
+    case 9: sweep_body<float, 512, 0>(b, k, blk, smem); break;
+    case 10: sweep_body<float, 1024, 0>(b, k, blk, smem); break;
+    case 11: sweep_body<float, 2048, 0>(b, k, blk, smem); break;
+    case 12: sweep_body<float, 4096, 0>(b, k, blk, smem); break;
+    default: break;
+    }
+}
+
 // x-advection by dt = b.a[sim] directly on the v-fastest layout f[nx][nv]
 // (N = nx): a block owns the x-lines j0 .. j0 + B - 1, i.e. the tile
 // f[0..N)[j0..j0+B), and runs the packed line-pair transform on B / 2 pairs
@@ -411,23 +453,24 @@ struct Fused {
     static constexpr int SKEW = sizeof(T) == 4 ? (VPR >= 16 ? 1 : 16 / VPR) : 8;
     static constexpr int LDSP = F::LDSN + SKEW; // per-array stride (bank skew)
     static constexpr int ITER = N * VPR / TB;   // tile vectors per thread
+    static constexpr int SMEM = PPB * 2 * LDSP + PPB * 2 * kTaps;
 };
 
 template <typename T, int N>
 constexpr int kFusedThreads = Fused<T, N>::TB;
 
+// Block hb of sim `sim`; smem holds Fused<T, N>::SMEM values.
 template <typename T, int N>
-__global__ __launch_bounds__((kFusedThreads<T, N>), (Fused<T, N>::WAVES)) void xsweep_fused_kernel(const Batch b) {
+__device__ __forceinline__ void xsweep_body(const Batch &b, int sim, int hb, T *smem) {
     using F = Fft<T, N>;
     using C = Fused<T, N>;
     constexpr int R = F::R, TPF = F::TPF;
-    __shared__ T lds[C::PPB * 2 * C::LDSP];
-    __shared__ T wsh[C::PPB][2][kTaps];
+    T *lds = smem;
+    T(*wsh)[2][kTaps] = reinterpret_cast<T(*)[2][kTaps]>(smem + C::PPB * 2 * C::LDSP);
 
-    const SimDev &S = *b.s[blockIdx.y];
+    const SimDev &S = *b.s[sim];
     const int nv = S.nv;
     const int ntiles = nv / C::B;
-    const int hb = blockIdx.x;
     if (hb >= ntiles) return;  // whole block idle
     const int tile = (ntiles % 8 == 0) ? (hb % 8) * (ntiles / 8) + hb / 8 : hb;
     const int j0 = tile * C::B;
@@ -440,7 +483,7 @@ __global__ __launch_bounds__((kFusedThreads<T, N>), (Fused<T, N>::WAVES)) void x
     const int slot = tid % C::PPB;
     const int t = tid / C::PPB;
     const int lineA = j0 + 2 * slot, lineB = lineA + 1;
-    const double dt = b.a[blockIdx.y];
+    const double dt = b.a[sim];
     long long bA, bB;
     double sA, sB;
     split_shift(-(S.vmin + lineA * S.dv) * dt * S.inv_dx, bA, sA);
@@ -502,6 +545,67 @@ __global__ __launch_bounds__((kFusedThreads<T, N>), (Fused<T, N>::WAVES)) void x
             *reinterpret_cast<double2 *>(dst) = double2{e[0], e[1]};
         }
     });
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__((kFusedThreads<T, N>), (Fused<T, N>::WAVES)) void xsweep_fused_kernel(const Batch b) {
+    __shared__ T smem[Fused<T, N>::SMEM];
+    xsweep_body<T, N>(b, (int)blockIdx.y, (int)blockIdx.x, smem);
+}
+
+// FP32 x-sweeps of sims with x-lines of 64 .. 1024 points in one launch
+// (256-thread blocks for all of them).  Each sim's first block is a multiple
+// of 8, so the XCD-aware tile order holds.
+__global__ __launch_bounds__(256, 3) void xsweep_mixed_kernel(const Batch b, const BlockMap m) {
+    __shared__ float smem[Fused<float, 64>::SMEM];  // the largest of 64 .. 1024
+    const int bid = (int)blockIdx.x;
+    const int k = mixed_sim(b, m, bid);
+    const int hb = bid - m.first[k];
+    switch (m.lgn[k]) {
+    case 6: xsweep_body<float, 64>(b, k, hb, smem); break;
+    case 7: xsweep_body<float, 128>(b, k, hb, smem); break;
+    case 8: xsweep_body<float, 256>(b, k, hb, smem); break;
+    case 9: xsweep_body<float, 512>(b, k, hb, smem); break;
+    case 10: xsweep_body<float, 1024>(b, k, hb, smem); break;
+    default: break;
+    }
+}
+
+static_assert(Fused<float, 64>::TB == 256 && Fused<float, 1024>::TB == 256 &&
+                  Fused<float, 64>::WAVES == 3 && Fused<float, 1024>::WAVES == 3,
+              "mixed x-sweep: 256-thread blocks at 3 waves for 64 .. 1024 points");
+static_assert(Fused<float, 64>::SMEM >= Fused<float, 128>::SMEM &&
+                  Fused<float, 64>::SMEM >= Fused<float, 256>::SMEM &&
+                  Fused<float, 64>::SMEM >= Fused<float, 512>::SMEM &&
+                  Fused<float, 64>::SMEM >= Fused<float, 1024>::SMEM,
+              "mixed x-sweep LDS");
+static_assert(Sweep<float, 64>::SMEM >= Sweep<float, 128>::SMEM &&
+                  Sweep<float, 64>::SMEM >= Sweep<float, 256>::SMEM &&
+                  Sweep<float, 64>::SMEM >= Sweep<float, 512>::SMEM &&
+                  Sweep<float, 64>::SMEM >= Sweep<float, 1024>::SMEM &&
+                  Sweep<float, 64>::SMEM >= Sweep<float, 2048>::SMEM &&
+                  Sweep<float, 64>::SMEM >= Sweep<float, 4096>::SMEM,
+              "mixed v-sweep LDS");
+
+bool sweep_mixed_ok(bool vsweep, int n) {
+    const int logn = ilog2(n);
+    return (1 << logn) == n && n >= 64 && n <= (vsweep ? 4096 : 1024);
+}
+
+int sweep_blocks_mixed(bool vsweep, int n, int lines) {
+    if (!sweep_mixed_ok(vsweep, n)) return 0;
+    if (vsweep) {
+        const int ppb = 256 / (n / fft_regs(n));
+        return (lines / 2 + ppb - 1) / ppb;
+    }
+    const int tiles = lines / (2 * (256 / (n / fft_regs(n))));
+    return (tiles + 7) / 8 * 8;
+}
+
+void launch_sweep_mixed(bool vsweep, const Batch &b, const BlockMap &m, hipStream_t st) {
+    const int blocks = m.first[b.n];
+    if (vsweep) hipLaunchKernelGGL(sweep_v_mixed_kernel, dim3(blocks), dim3(256), 0, st, b, m);
+    else hipLaunchKernelGGL(xsweep_mixed_kernel, dim3(blocks), dim3(256), 0, st, b, m);
 }
 
 template <typename T, int N>
@@ -688,6 +792,9 @@ __global__ __launch_bounds__(kFieldThreads<N>) void field_kernel(const Batch b) 
         constexpr int r = decltype(rc)::value;
         v[r] = cx<double>{rho[t + r * TPF], 0.0};
     });
+    // All twiddles of both transforms, requested together with rho.
+    typename F::Rows rows;
+    F::load_rows(t, tab, rows);
     // 1/(N k_m) for this thread's modes, requested now so that the loads
     // overlap the forward transform (Fourier solve only).
     double ik[R];
@@ -698,7 +805,7 @@ __global__ __launch_bounds__(kFieldThreads<N>) void field_kernel(const Batch b) 
             ik[k] = invk[t + TPF * k];
         });
     }
-    F::template run<-1>(v, t, lre, lim, tab);
+    F::template run<-1>(v, t, lre, lim, rows);
 
     // rho_hat_0 .. rho_hat_7 (unnormalised here).
     static_for<0, R>([&](auto ic) {
@@ -766,7 +873,7 @@ __global__ __launch_bounds__(kFieldThreads<N>) void field_kernel(const Batch b) 
             constexpr int k = F::kpos(i);
             Y[k] = cx<double>{v[i].im * ik[k], -v[i].re * ik[k]};
         });
-        F::template run<1>(Y, t, lre, lim, tab);
+        F::template run<1>(Y, t, lre, lim, rows);
         static_for<0, R>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
             e[i] = Y[i].re;

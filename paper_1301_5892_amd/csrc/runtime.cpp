@@ -398,6 +398,44 @@ int run_sweep(vog_sim *lead, const std::vector<vog_sim *> &sims, const std::vect
         groups[key].sims.push_back(s);
         groups[key].arg.push_back(arg[k]);
     }
+    // FP32 groups of different line lengths that one launch covers: merged
+    // when there are two or more of them (a single length keeps its own kernel).
+    auto mixable = [&](const std::pair<int, int> &key) {
+        const bool fp64 = (key.first & 1) != 0;
+        const int xmode = key.first / 2;
+        return !fp64 && (vsweep || xmode == X_TILED) && sweep_mixed_ok(vsweep, key.second);
+    };
+    Group mixed;
+    {
+        std::vector<std::pair<int, int>> keys;
+        for (auto &kv : groups)
+            if (mixable(kv.first)) keys.push_back(kv.first);
+        if (keys.size() >= 2) {
+            for (auto it = keys.rbegin(); it != keys.rend(); ++it) {  // longest lines first
+                Group &g = groups[*it];
+                mixed.sims.insert(mixed.sims.end(), g.sims.begin(), g.sims.end());
+                mixed.arg.insert(mixed.arg.end(), g.arg.begin(), g.arg.end());
+                groups.erase(*it);
+            }
+        }
+    }
+    if (!mixed.sims.empty()) {
+        int rc = for_chunks(mixed, [&](const Batch &b, size_t base) {
+            BlockMap m{};
+            for (int k = 0; k < b.n; ++k) {
+                const vog_sim *s = mixed.sims[base + k];
+                const int n = vsweep ? s->cfg.nv : s->cfg.nx;
+                m.lgn[k] = ilog2(n);
+                m.first[k + 1] = m.first[k] + sweep_blocks_mixed(vsweep, n, vsweep ? s->cfg.nx : s->cfg.nv);
+            }
+            EventPair *p;
+            prof_begin(lead, vsweep ? K_SWEEP_V : K_SWEEP_X, &p);
+            launch_sweep_mixed(vsweep, b, m, lead->stream);
+            prof_end(lead, p);
+            return check_launch();
+        });
+        if (rc != VOG_OK) return rc;
+    }
     for (auto &kv : groups) {
         const bool fp64 = (kv.first.first & 1) != 0;
         const int xmode = kv.first.first / 2;

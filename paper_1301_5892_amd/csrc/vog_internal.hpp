@@ -55,6 +55,14 @@ struct Batch {
     double drv_ph[kMaxBatch];   // omega t (field solve)
 };
 
+// Blocks of one launch over FP32 sims whose lines have different lengths:
+// sim k owns the blocks first[k] .. first[k+1] - 1 and its lines have
+// 2^lgn[k] points.
+struct BlockMap {
+    int first[kMaxBatch + 1];
+    int lgn[kMaxBatch];
+};
+
 enum Kind { K_SWEEP_V = 0, K_SWEEP_X = 1, K_T_VX = 2, K_T_XV = 3, K_FIELD = 4, K_MOMENTS = 5, K_RHO = 6 };
 
 // Host-side launchers (defined in kernels.hip).
@@ -65,6 +73,13 @@ int fused_lines_per_block(bool fp64, int nx);
 LaunchFn fused_xsweep_launcher(bool fp64, int nx);
 void launch_transpose(bool fp64, bool to_v, const Batch &b, int max_tiles, hipStream_t st);
 LaunchFn field_launcher(int nx);
+// One launch of FP32 v-sweeps (lines of 64 .. 4096 points) or FP32 x-sweeps on
+// the v-fastest layout (64 .. 1024 points) over sims of mixed line lengths.
+// Blocks per sim: sweep_blocks_mixed(vsweep, n, lines) for lines of n points
+// (v-sweep: lines = nx; x-sweep: lines = nv).
+int sweep_blocks_mixed(bool vsweep, int n, int lines);
+bool sweep_mixed_ok(bool vsweep, int n);
+void launch_sweep_mixed(bool vsweep, const Batch &b, const BlockMap &m, hipStream_t st);
 void launch_rho_v(bool fp64, const Batch &b, int max_nx, hipStream_t st);
 void launch_rho_reduce(const Batch &b, int max_nx, hipStream_t st);
 void launch_moments(bool fp64, const Batch &b, int max_nx, hipStream_t st);

@@ -375,3 +375,68 @@ def test_bump_on_tail_mass_error_ordering(gpu, capsys):
     assert err["fp32_deltaf"][1] < err["fp32_plain"][1]
     for k in ("fp32_deltaf", "fp32_plain"):
         assert err[k][1] > err[k][0]          # it accumulates
+
+
+# ---------------------------------------------------------------- mixed line lengths
+
+# FP32 sims whose lines differ in length share one sweep launch per phase (every
+# v-line length from 64 to 4096 points, x-lines from 64 to 1024 points on the
+# v-fastest layout).  Each sim must come out exactly as when stepped alone.
+def _mixed_fp32():
+    base = workloads.landau_weak()
+    return [base.replace(nx=64, nv=4096, precision="fp32_deltaf"),
+            base.replace(nx=1024, nv=128, precision="fp32_deltaf"),
+            base.replace(nx=128, nv=2048, precision="fp32_deltaf"),
+            base.replace(nx=256, nv=256, precision="fp32_deltaf"),
+            base.replace(nx=512, nv=512, precision="fp32_deltaf"),
+            base.replace(nx=64, nv=128, precision="fp32_plain"),
+            spline(base.replace(nx=128, nv=1024, precision="fp32_deltaf"), 5),
+            base.replace(nx=32, nv=64, precision="fp32_deltaf")]
+
+
+def test_mixed_lengths_batch_equals_alone(gpu):
+    from paper_1301_5892_amd import vog
+    ws = _mixed_fp32()
+    alone = []
+    for w in ws:
+        s = gpu.Sim(w).init()
+        s.step(6)
+        alone.append((s.get_raw(), s.get_E()))
+    sims = [gpu.Sim(w).init() for w in ws]
+    vog.step_batch(sims, 6)
+    for w, s, (f0, e0) in zip(ws, sims, alone):
+        assert np.array_equal(s.get_raw(), f0), w.name
+        assert np.array_equal(s.get_E(), e0), w.name
+
+
+def test_mixed_lengths_batch_matches_oracle(gpu):
+    from paper_1301_5892_amd import vog
+    ws = _mixed_fp32()
+    sims = [gpu.Sim(w).init() for w in ws]
+    vog.step_batch(sims, 3)
+    for w, s in zip(ws, sims):
+        if w.nx * w.nv > 128 * 1024:
+            continue
+        o = oracle.Oracle(w).init()
+        o.step(3)
+        # stored arrays: delta f for the delta-f variants, f for plain FP32
+        assert rel(s.get_raw(), o.f) < TOL32, w.name
+        assert rel_field(s.get_E(), o) < TOL32, w.name
+
+
+def test_mixed_lengths_more_sims_than_one_launch(gpu):
+    # 40 sims: the mixed launches split into chunks of at most 32 sims.
+    from paper_1301_5892_amd import vog
+    base = workloads.landau_weak()
+    sizes = [(64, 128), (128, 256), (64, 512), (256, 128)]
+    ws = [base.replace(nx=sizes[i % 4][0], nv=sizes[i % 4][1], precision="fp32_deltaf",
+                       amp=(0.01 + 0.001 * i,)) for i in range(40)]
+    alone = []
+    for w in ws[:4] + ws[-4:]:
+        s = gpu.Sim(w).init()
+        s.step(4)
+        alone.append(s.get_raw())
+    sims = [gpu.Sim(w).init() for w in ws]
+    vog.step_batch(sims, 4)
+    for s, f0 in zip(sims[:4] + sims[-4:], alone):
+        assert np.array_equal(s.get_raw(), f0)
