@@ -756,18 +756,29 @@ template <int N>
 constexpr int kFieldThreads = Fft<double, N>::TPF;
 
 template <int N>
-__global__ __launch_bounds__(kFieldThreads<N>) void field_kernel(const Batch b) {
+struct Field {
+    using F = Fft<double, N>;
+    static constexpr int TPF = F::TPF;
+    static constexpr int NW = (TPF + 63) / 64;  // waves in the block
+    // LDS (doubles): lre, lim, red, scan, modes, bad flag
+    static constexpr int SMEM = 2 * F::LDSN + NW + TPF + 16 + 1;
+};
+
+// Field solve of sim `sim` by threads t = 0 .. TPF - 1 (all of them must call
+// it); smem holds Field<N>::SMEM doubles.
+template <int N>
+__device__ __forceinline__ void field_body(const Batch &b, int sim, double *smem) {
     using F = Fft<double, N>;
     constexpr int R = F::R, TPF = F::TPF;
-    constexpr int NW = (TPF + 63) / 64;  // waves in the block
+    constexpr int NW = Field<N>::NW;
     constexpr int WL = TPF < 64 ? TPF : 64;
-    __shared__ double lre[F::LDSN], lim[F::LDSN];
-    __shared__ double red[NW];
-    __shared__ double scan[TPF];
-    __shared__ double modes[8][2];
-    __shared__ int bad[1];
+    double *lre = smem, *lim = smem + F::LDSN;
+    double *red = lim + F::LDSN;
+    double *scan = red + NW;
+    double(*modes)[2] = reinterpret_cast<double(*)[2]>(scan + TPF);
+    int *bad = reinterpret_cast<int *>(scan + TPF + 16);
 
-    const SimDev &S = *b.s[blockIdx.x];
+    const SimDev &S = *b.s[sim];
     const int t = threadIdx.x;
     const cx<double> *tab = (const cx<double> *)S.tw_x64;
     if (t == 0) bad[0] = 0;
@@ -882,7 +893,7 @@ __global__ __launch_bounds__(kFieldThreads<N>) void field_kernel(const Batch b) 
 
     double e2 = 0.0;
     bool finite = true;
-    const double damp = b.drv_amp[blockIdx.x], dph = b.drv_ph[blockIdx.x];
+    const double damp = b.drv_amp[sim], dph = b.drv_ph[sim];
     static_for<0, R>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         const int j = t + TPF * F::kpos(i);
@@ -898,8 +909,8 @@ __global__ __launch_bounds__(kFieldThreads<N>) void field_kernel(const Batch b) 
     if (t == 0) {
         const double invn = 1.0 / (double)N;
         vog_diag d;
-        d.step = b.step[blockIdx.x];
-        d.t = b.t[blockIdx.x];
+        d.step = b.step[sim];
+        d.t = b.t[sim];
         d.normE = sqrt(S.dx * e2);
         d.rho0 = modes[0][0] * invn;
         d.abs_rho1 = sqrt(modes[1][0] * modes[1][0] + modes[1][1] * modes[1][1]) * invn;
@@ -915,20 +926,50 @@ __global__ __launch_bounds__(kFieldThreads<N>) void field_kernel(const Batch b) 
 }
 
 template <int N>
+__global__ __launch_bounds__(kFieldThreads<N>) void field_kernel(const Batch b) {
+    __shared__ double smem[Field<N>::SMEM];
+    field_body<N>(b, (int)blockIdx.x, smem);
+}
+
+// Field solves of sims with 8 .. 1024 points in x, any mix of lengths, in
+// one launch: one wave per sim, whose first TPF lanes run the body of the
+// sim's length (a one-wave block needs no barrier between its lanes).
+__global__ __launch_bounds__(64) void field_mixed_kernel(const Batch b, const BlockMap m) {
+    __shared__ double smem[Field<1024>::SMEM];
+    const int k = (int)blockIdx.x;
+    const int t = (int)threadIdx.x;
+    switch (m.lgn[k]) {
+    case 3: if (t < Field<8>::TPF) field_body<8>(b, k, smem); break;
+    case 4: if (t < Field<16>::TPF) field_body<16>(b, k, smem); break;
+    case 5: if (t < Field<32>::TPF) field_body<32>(b, k, smem); break;
+    case 6: if (t < Field<64>::TPF) field_body<64>(b, k, smem); break;
+    case 7: if (t < Field<128>::TPF) field_body<128>(b, k, smem); break;
+    case 8: if (t < Field<256>::TPF) field_body<256>(b, k, smem); break;
+    case 9: if (t < Field<512>::TPF) field_body<512>(b, k, smem); break;
+    case 10: field_body<1024>(b, k, smem); break;
+    default: break;
+    }
+}
+
+static_assert(Field<1024>::TPF == 64 && Field<1024>::SMEM >= Field<512>::SMEM,
+              "mixed field solve: one wave, LDS of the 1024-point body");
+
+bool field_mixed_ok(int nx) { return nx >= 8 && nx <= 1024 && (nx & (nx - 1)) == 0; }
+
+void launch_field_mixed(const Batch &b, const BlockMap &m, hipStream_t st) {
+    hipLaunchKernelGGL(field_mixed_kernel, dim3(b.n), dim3(64), 0, st, b, m);
+}
+
+template <int N>
 static void launch_field(const Batch &b, int, hipStream_t st) {
     hipLaunchKernelGGL((field_kernel<N>), dim3(b.n), dim3(Fft<double, N>::TPF), 0, st, b);
 }
 
-template <int... L>
-static LaunchFn pick_field(int logn, std::integer_sequence<int, L...>) {
-    LaunchFn fns[] = {&launch_field<(8 << L)>...};
-    return fns[logn - 3];
-}
-
+// x-lines of 2048 and 4096 points (shorter ones go through field_mixed_kernel).
 LaunchFn field_launcher(int nx) {
-    const int logn = ilog2(nx);
-    if (nx < VOG_MIN_N || nx > VOG_MAX_N || (1 << logn) != nx) return nullptr;
-    return pick_field(logn, std::make_integer_sequence<int, 10>{});
+    if (nx == 2048) return &launch_field<2048>;
+    if (nx == 4096) return &launch_field<4096>;
+    return nullptr;
 }
 
 // ----------------------------------------------------------------- rho (v layout)

@@ -502,14 +502,26 @@ int run_rho_reduce(vog_sim *lead, const std::vector<vog_sim *> &sims) {
 // Field solve (Poisson, E, diagnostics record) for all sims.
 int run_field(vog_sim *lead, const std::vector<vog_sim *> &sims, const std::vector<int64_t> &stepno,
               const std::vector<double> &tnow) {
-    std::map<int, std::vector<size_t>> groups;  // nx -> indices
-    for (size_t k = 0; k < sims.size(); ++k) groups[sims[k]->cfg.nx].push_back(k);
+    // nx -> indices; every nx of at most 1024 points goes to key 0, the
+    // one-wave kernel that covers all of them (also for a single sim, so that a
+    // sim gives the same bits alone and in a batch).
+    std::map<int, std::vector<size_t>> groups;
+    for (size_t k = 0; k < sims.size(); ++k) {
+        const int nx = sims[k]->cfg.nx;
+        groups[field_mixed_ok(nx) ? 0 : nx].push_back(k);
+    }
+    if (groups.count(0)) {  // longest lines first
+        std::vector<size_t> &g = groups[0];
+        std::stable_sort(g.begin(), g.end(),
+                         [&](size_t a, size_t c) { return sims[a]->cfg.nx > sims[c]->cfg.nx; });
+    }
     for (auto &kv : groups) {
-        LaunchFn fn = field_launcher(kv.first);
-        if (!fn) return fail(VOG_EINVAL, "no field kernel for this nx");
+        LaunchFn fn = kv.first == 0 ? nullptr : field_launcher(kv.first);
+        if (kv.first != 0 && !fn) return fail(VOG_EINVAL, "no field kernel for this nx");
         const auto &idx = kv.second;
         for (size_t base = 0; base < idx.size(); base += kMaxBatch) {
             Batch b{};
+            BlockMap m{};
             b.n = (int)std::min<size_t>(kMaxBatch, idx.size() - base);
             for (int k = 0; k < b.n; ++k) {
                 const size_t i = idx[base + k];
@@ -517,10 +529,13 @@ int run_field(vog_sim *lead, const std::vector<vog_sim *> &sims, const std::vect
                 b.step[k] = stepno[i];
                 b.t[k] = tnow[i];
                 drive_at(sims[i]->cfg, tnow[i], &b.drv_amp[k], &b.drv_ph[k]);
+                m.first[k + 1] = k + 1;
+                m.lgn[k] = ilog2(sims[i]->cfg.nx);
             }
             EventPair *p;
             prof_begin(lead, K_FIELD, &p);
-            fn(b, 0, lead->stream);
+            if (fn) fn(b, 0, lead->stream);
+            else launch_field_mixed(b, m, lead->stream);
             prof_end(lead, p);
             int rc = check_launch();
             if (rc != VOG_OK) return rc;

@@ -72,7 +72,7 @@ LaunchFn sweep_launcher(bool fp64, int n, bool vsweep);
 int fused_lines_per_block(bool fp64, int nx);
 LaunchFn fused_xsweep_launcher(bool fp64, int nx);
 void launch_transpose(bool fp64, bool to_v, const Batch &b, int max_tiles, hipStream_t st);
-LaunchFn field_launcher(int nx);
+LaunchFn field_launcher(int nx);  // nx = 2048, 4096
 // One launch of FP32 v-sweeps (lines of 64 .. 4096 points) or FP32 x-sweeps on
 // the v-fastest layout (64 .. 1024 points) over sims of mixed line lengths.
 // Blocks per sim: sweep_blocks_mixed(vsweep, n, lines) for lines of n points
@@ -80,6 +80,10 @@ LaunchFn field_launcher(int nx);
 int sweep_blocks_mixed(bool vsweep, int n, int lines);
 bool sweep_mixed_ok(bool vsweep, int n);
 void launch_sweep_mixed(bool vsweep, const Batch &b, const BlockMap &m, hipStream_t st);
+// One launch of field solves over sims of 8 .. 1024 points in x, of one or
+// several lengths (block k = sim k, m.lgn[k] = log2 nx).
+bool field_mixed_ok(int nx);
+void launch_field_mixed(const Batch &b, const BlockMap &m, hipStream_t st);
 void launch_rho_v(bool fp64, const Batch &b, int max_nx, hipStream_t st);
 void launch_rho_reduce(const Batch &b, int max_nx, hipStream_t st);
 void launch_moments(bool fp64, const Batch &b, int max_nx, hipStream_t st);
