@@ -10,7 +10,7 @@ namespace vog {
 
 constexpr int kDMax = 8;                 // Lagrange 2d+1 with d <= 8
 constexpr int kTaps = 2 * kDMax + 2;     // 18 stencil offsets q = -8 .. 9
-constexpr int kMaxBatch = 32;            // sims per grouped launch
+constexpr int kMaxBatch = 64;            // sims per grouped launch
 constexpr int kRingCap = 4096;           // diagnostics records kept per sim
 constexpr int kTile = 64;                // transpose tile edge
 

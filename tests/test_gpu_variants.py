@@ -425,12 +425,12 @@ def test_mixed_lengths_batch_matches_oracle(gpu):
 
 
 def test_mixed_lengths_more_sims_than_one_launch(gpu):
-    # 40 sims: the mixed launches split into chunks of at most 32 sims.
+    # 72 sims: the mixed launches split into chunks of at most 64 sims.
     from paper_1301_5892_amd import vog
     base = workloads.landau_weak()
     sizes = [(64, 128), (128, 256), (64, 512), (256, 128)]
     ws = [base.replace(nx=sizes[i % 4][0], nv=sizes[i % 4][1], precision="fp32_deltaf",
-                       amp=(0.01 + 0.001 * i,)) for i in range(40)]
+                       amp=(0.01 + 0.001 * i,)) for i in range(72)]
     alone = []
     for w in ws[:4] + ws[-4:]:
         s = gpu.Sim(w).init()
