@@ -398,11 +398,15 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && N >= 32 ? 3 : 1)) void swee
     sweep_body<T, N, KIND>(b, (int)blockIdx.y, (int)blockIdx.x, smem);
 }
 
-// Sim of block bid in a launch over mixed line lengths (m.first ascending).
+// Sim of block bid in a launch over mixed line lengths (m.first ascending,
+// m.first[0] = 0): the number of j in 1 .. n-1 with first[j] <= bid, one
+// candidate j per lane of the wave, counted with a ballot.  All 64 lanes of
+// the wave must call it.
+static_assert(kMaxBatch <= 64, "one lane per candidate sim");
 __device__ __forceinline__ int mixed_sim(const Batch &b, const BlockMap &m, int bid) {
-    int k = 0;
-    while (k + 1 < b.n && m.first[k + 1] <= bid) ++k;
-    return k;
+    const int j = (int)(threadIdx.x & 63) + 1;
+    const bool le = j < b.n && m.first[j] <= bid;
+    return __builtin_amdgcn_readfirstlane(__popcll(__ballot(le)));
 }
 
 // FP32 v-sweeps of sims with lines of 64 .. 4096 points in one launch: every
@@ -936,7 +940,7 @@ __global__ __launch_bounds__(kFieldThreads<N>) void field_kernel(const Batch b) 
 // sim's length (a one-wave block needs no barrier between its lanes).
 __global__ __launch_bounds__(64) void field_mixed_kernel(const Batch b, const BlockMap m) {
     __shared__ double smem[Field<1024>::SMEM];
-    const int k = (int)blockIdx.x;
+    const int k = (int)blockIdx.x;  // one block per sim
     const int t = (int)threadIdx.x;
     switch (m.lgn[k]) {
     case 3: if (t < Field<8>::TPF) field_body<8>(b, k, smem); break;
