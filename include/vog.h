@@ -140,7 +140,9 @@ size_t vog_workspace_bytes(const vog_config *cfg);
  * caller, which must keep it alive until vog_destroy; or NULL, in which case
  * the library allocates and owns it.  hip_stream: the hipStream_t all work of
  * this sim is enqueued on (borrowed, must outlive the sim).  The state is
- * zero until vog_init_perturbed, vog_set_f or vog_set_state. */
+ * zero until vog_init_perturbed, vog_set_f or vog_set_state.  The tables are
+ * uploaded asynchronously from copies the library keeps, so the call does not
+ * wait for work already queued on the stream. */
 int vog_create(const vog_config *cfg, void *dev_workspace, size_t bytes,
                void *hip_stream, vog_sim **out);
 

@@ -350,12 +350,13 @@ __device__ __forceinline__ void sweep_body(const Batch &b, int sim, int blk, T *
     split_shift(betaB, bB, sB);
     pair_weights<T, N, TPF>(S.d, S.interp, sA, sB, t, wsh[slot][0], wsh[slot][1]);
 
-    // Load the two lines packed as z = uA + i uB.
+    // Load the two lines packed as z = uA + i uB (a slot past the last pair
+    // reads lines 0 and 1 and stores nothing).
     cx<T> v[R];
     static_for<0, R>([&](auto rc) {
         constexpr int r = decltype(rc)::value;
         const int j = t + r * TPF;
-        v[r] = active ? cx<T>{pA[j], pB[j]} : cx<T>{(T)0, (T)0};
+        v[r] = cx<T>{pA[j], pB[j]};
     });
 
     cx<T> Y[R];

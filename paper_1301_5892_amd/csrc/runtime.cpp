@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <deque>
 #include <map>
 #include <string>
 #include <vector>
@@ -186,6 +187,10 @@ struct vog_sim {
     SimDev host_dev;       // host copy of the device constants
     const SimDev *dev;     // device address
     std::vector<double> feq64;  // f_eq(v_j), FP64
+    // Host copies of the tables uploaded by vog_create, kept until the copies
+    // are known to be done (the next synchronisation), so that creating a sim
+    // does not wait for work already queued on the stream.
+    std::deque<std::vector<char>> staging;
     int64_t step;
     double t;
     int64_t diag_read;     // records consumed by vog_get_diag
@@ -314,9 +319,17 @@ std::vector<T> eps_rows(int n) {
     return out;
 }
 
+
+// Copies bytes into a host buffer owned by the sim and queues their upload
+// (the buffer lives until the sim's next synchronisation).
+int stage(vog_sim *s, char *dst, const void *src, size_t bytes) {
+    s->staging.emplace_back((const char *)src, (const char *)src + bytes);
+    return upload(dst, s->staging.back().data(), bytes, s->stream);
+}
+
 template <typename T>
-int upload_vec(char *dst, const std::vector<T> &v, hipStream_t st) {
-    return upload(dst, v.data(), v.size() * sizeof(T), st);
+int stage_vec(vog_sim *s, char *dst, const std::vector<T> &v) {
+    return stage(s, dst, v.data(), v.size() * sizeof(T));
 }
 
 // Profiling helpers: events around one grouped launch of a kind.
@@ -815,7 +828,8 @@ int vog_create(const vog_config *c, void *dev_workspace, size_t bytes, void *hip
     };
     launch_fill(s->ws, L.total, s->stream);
     if ((rc = check_launch()) != VOG_OK) return bail(rc);
-    // Staging vectors stay alive until the synchronisation below.
+    // The tables are uploaded from copies the sim owns (stage), so nothing here
+    // waits for work already queued on the stream.
     const std::vector<double> tw64x = twiddle_rows<double>(nx);
     const std::vector<double> tw64v = twiddle_rows<double>(nv);
     const std::vector<double> ep64x = eps_rows<double>(nx);
@@ -826,34 +840,34 @@ int vog_create(const vog_config *c, void *dev_workspace, size_t bytes, void *hip
         id64x = bspline_inverse_symbol(nx, c->degree);
         id64v = bspline_inverse_symbol(nv, c->degree);
         if (fp64) {
-            if ((rc = upload_vec(s->ws + L.iden_x, id64x, s->stream)) != VOG_OK) return bail(rc);
-            if ((rc = upload_vec(s->ws + L.iden_v, id64v, s->stream)) != VOG_OK) return bail(rc);
+            if ((rc = stage_vec(s, s->ws + L.iden_x, id64x)) != VOG_OK) return bail(rc);
+            if ((rc = stage_vec(s, s->ws + L.iden_v, id64v)) != VOG_OK) return bail(rc);
         } else {
             id32x.assign(id64x.begin(), id64x.end());
             id32v.assign(id64v.begin(), id64v.end());
-            if ((rc = upload_vec(s->ws + L.iden_x, id32x, s->stream)) != VOG_OK) return bail(rc);
-            if ((rc = upload_vec(s->ws + L.iden_v, id32v, s->stream)) != VOG_OK) return bail(rc);
+            if ((rc = stage_vec(s, s->ws + L.iden_x, id32x)) != VOG_OK) return bail(rc);
+            if ((rc = stage_vec(s, s->ws + L.iden_v, id32v)) != VOG_OK) return bail(rc);
         }
     }
     if (fp64) {
-        if ((rc = upload_vec(s->ws + L.tw_x, tw64x, s->stream)) != VOG_OK) return bail(rc);
-        if ((rc = upload_vec(s->ws + L.tw_v, tw64v, s->stream)) != VOG_OK) return bail(rc);
-        if ((rc = upload_vec(s->ws + L.eps_x, ep64x, s->stream)) != VOG_OK) return bail(rc);
-        if ((rc = upload_vec(s->ws + L.eps_v, ep64v, s->stream)) != VOG_OK) return bail(rc);
-        if ((rc = upload_vec(s->ws + L.feq_g, fg64, s->stream)) != VOG_OK) return bail(rc);
+        if ((rc = stage_vec(s, s->ws + L.tw_x, tw64x)) != VOG_OK) return bail(rc);
+        if ((rc = stage_vec(s, s->ws + L.tw_v, tw64v)) != VOG_OK) return bail(rc);
+        if ((rc = stage_vec(s, s->ws + L.eps_x, ep64x)) != VOG_OK) return bail(rc);
+        if ((rc = stage_vec(s, s->ws + L.eps_v, ep64v)) != VOG_OK) return bail(rc);
+        if ((rc = stage_vec(s, s->ws + L.feq_g, fg64)) != VOG_OK) return bail(rc);
     } else {
         tw32x = twiddle_rows<float>(nx);
         tw32v = twiddle_rows<float>(nv);
         ep32x = eps_rows<float>(nx);
         ep32v = eps_rows<float>(nv);
         fg32.assign(fg64.begin(), fg64.end());
-        if ((rc = upload_vec(s->ws + L.tw_x, tw32x, s->stream)) != VOG_OK) return bail(rc);
-        if ((rc = upload_vec(s->ws + L.tw_v, tw32v, s->stream)) != VOG_OK) return bail(rc);
-        if ((rc = upload_vec(s->ws + L.eps_x, ep32x, s->stream)) != VOG_OK) return bail(rc);
-        if ((rc = upload_vec(s->ws + L.eps_v, ep32v, s->stream)) != VOG_OK) return bail(rc);
-        if ((rc = upload_vec(s->ws + L.feq_g, fg32, s->stream)) != VOG_OK) return bail(rc);
+        if ((rc = stage_vec(s, s->ws + L.tw_x, tw32x)) != VOG_OK) return bail(rc);
+        if ((rc = stage_vec(s, s->ws + L.tw_v, tw32v)) != VOG_OK) return bail(rc);
+        if ((rc = stage_vec(s, s->ws + L.eps_x, ep32x)) != VOG_OK) return bail(rc);
+        if ((rc = stage_vec(s, s->ws + L.eps_v, ep32v)) != VOG_OK) return bail(rc);
+        if ((rc = stage_vec(s, s->ws + L.feq_g, fg32)) != VOG_OK) return bail(rc);
     }
-    if ((rc = upload_vec(s->ws + L.tw_x64, tw64x, s->stream)) != VOG_OK) return bail(rc);
+    if ((rc = stage_vec(s, s->ws + L.tw_x64, tw64x)) != VOG_OK) return bail(rc);
     // 1 / (nx k_m) for the Fourier field solve: k_m = 2 pi mt / L with mt the
     // signed mode index; modes 0 and nx/2 (and every mode for a zero field) get 0.
     std::vector<double> invk(nx, 0.0);
@@ -863,11 +877,9 @@ int vog_create(const vog_config *c, void *dev_workspace, size_t bytes, void *hip
             const int mt = 2 * m < nx ? m : m - nx;
             invk[m] = 1.0 / ((double)nx * (2.0 * M_PI * (double)mt / c->L));
         }
-    if ((rc = upload_vec(s->ws + L.invk, invk, s->stream)) != VOG_OK) return bail(rc);
-    if ((rc = upload_vec(s->ws + L.feq64, s->feq64, s->stream)) != VOG_OK) return bail(rc);
-    if ((rc = upload(s->ws + L.dev, &D, sizeof(D), s->stream)) != VOG_OK) return bail(rc);
-    // The staging vectors above are temporaries: wait until the copies are done.
-    if (hipStreamSynchronize(s->stream) != hipSuccess) return bail(fail(VOG_EDEVICE, "sync failed"));
+    if ((rc = stage_vec(s, s->ws + L.invk, invk)) != VOG_OK) return bail(rc);
+    if ((rc = stage_vec(s, s->ws + L.feq64, s->feq64)) != VOG_OK) return bail(rc);
+    if ((rc = stage(s, s->ws + L.dev, &D, sizeof(D))) != VOG_OK) return bail(rc);
     *out = s;
     return VOG_OK;
 }
@@ -1090,6 +1102,7 @@ int vog_sync(vog_sim *s) {
     int rc = device_guard(s);
     if (rc != VOG_OK) return rc;
     HIP_TRY(hipStreamSynchronize(s->stream));
+    s->staging.clear();
     if (s->step > 0 && s->host_dev.field_zero == 0) {
         vog_diag d;
         HIP_TRY(hipMemcpy(&d, s->host_dev.ring + (s->step % kRingCap), sizeof(d), hipMemcpyDeviceToHost));

@@ -10,6 +10,12 @@ across the whole active set).  Finished, failed or cancelled simulations are
 retired between quanta, which frees their memory and slot for the next
 admission.  Latency of a request = completion time - arrival time.
 
+With an executor that can launch a quantum and wait for it separately
+(`launch`, `wait`), admission also runs while a quantum executes: the slots of
+simulations that complete in that quantum are refilled then (their memory is
+still counted against the budget), and the new simulations join the next
+quantum, so creating them overlaps the device work.
+
 The scheduler talks to an executor; `GpuExecutor` drives libvog on the
 current torch stream.  Per-simulation arithmetic does not depend on which
 other simulations share a launch, so each result equals the result of the
@@ -80,11 +86,13 @@ class Scheduler:
         outcomes: Dict[int, Outcome] = {}
         used = 0
         t0 = self.ex.now()
+        overlap = hasattr(self.ex, "launch") and hasattr(self.ex, "wait")
 
         def now() -> float:
             return self.ex.now() - t0
 
-        while pending or waiting or active:
+        def intake() -> None:
+            nonlocal waiting
             tnow = now()
             while pending and pending[0].arrival <= tnow:
                 waiting.append(pending.popleft())
@@ -97,8 +105,11 @@ class Scheduler:
                     else:
                         keep.append(r)
                 waiting = keep
-            # admission in arrival order
-            while waiting and len(active) < self.max_active:
+
+        def admit(into: List[_Active], slots: int) -> None:
+            # admission in arrival order into at most `slots` free slots
+            nonlocal used
+            while waiting and slots > 0:
                 r = waiting[0]
                 fp = self.ex.footprint(r.workload)
                 if fp > self.budget:
@@ -109,10 +120,18 @@ class Scheduler:
                     break
                 waiting.popleft()
                 h = self.ex.start(r)
-                active.append(_Active(r, h, r.workload.nsteps, fp, now()))
+                into.append(_Active(r, h, r.workload.nsteps, fp, now()))
                 used += fp
-            self.stats["max_active"] = max(self.stats["max_active"], len(active))
+                slots -= 1
             self.stats["max_bytes"] = max(self.stats["max_bytes"], used)
+
+        incoming: List[_Active] = []
+        while pending or waiting or active or incoming:
+            active.extend(incoming)
+            incoming = []
+            intake()
+            admit(active, self.max_active - len(active))
+            self.stats["max_active"] = max(self.stats["max_active"], len(active))
             self.stats["max_queue"] = max(self.stats["max_queue"], len(waiting))
             if not active:
                 if pending:
@@ -120,7 +139,14 @@ class Scheduler:
                 continue
             # one quantum for every active sim
             counts = [min(self.quantum, a.remaining) for a in active]
-            self.ex.advance([a.handle for a in active], counts)
+            if overlap:
+                self.ex.launch([a.handle for a in active], counts)
+                ending = sum(c == a.remaining for a, c in zip(active, counts))
+                intake()
+                admit(incoming, self.max_active - (len(active) - ending))
+                self.ex.wait()
+            else:
+                self.ex.advance([a.handle for a in active], counts)
             self.stats["quanta"] += 1
             check = self.stats["quanta"] % self.check_every == 0
             tq = now()
@@ -176,13 +202,20 @@ class GpuExecutor:
     def start(self, req):
         return self.vog.Sim(req.workload, moments_every=self.moments_every).init()
 
-    def advance(self, handles, counts) -> None:
+    def launch(self, handles, counts) -> None:
+        """Enqueues one quantum (grouped by step count) without waiting."""
         groups: Dict[int, list] = {}
         for h, c in zip(handles, counts):
             groups.setdefault(c, []).append(h)
         for c, hs in sorted(groups.items(), reverse=True):
             self.vog.step_batch(hs, c)
+
+    def wait(self) -> None:
         self.torch.cuda.synchronize()
+
+    def advance(self, handles, counts) -> None:
+        self.launch(handles, counts)
+        self.wait()
 
     def failed(self, h) -> bool:
         try:
