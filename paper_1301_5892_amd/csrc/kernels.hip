@@ -898,13 +898,34 @@ __device__ __forceinline__ void field_body(const Batch &b, int sim, double *smem
 
     double e2 = 0.0;
     bool finite = true;
-    const double damp = b.drv_amp[sim], dph = b.drv_ph[sim];
+    // drive: E_app(t, x_j) = damp sin(k x_j - dph) from the table of
+    // sin(k x_j), cos(k x_j) (all of this thread's entries requested before
+    // any store) and one sincos of dph
+    const double damp = b.drv_amp[sim];
+    double app[R];
+    if (damp != 0.0) {
+        double sph, cph;
+        sincos(b.drv_ph[sim], &sph, &cph);
+        typedef double v2d __attribute__((ext_vector_type(2)));
+        const gmem<v2d> *sc = as_global(reinterpret_cast<const v2d *>(S.drv_sc));
+        v2d w[R];
+        static_for<0, R>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            w[i] = sc[t + TPF * F::kpos(i)];
+        });
+        static_for<0, R>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            app[i] = damp * (w[i].x * cph - w[i].y * sph);
+        });
+    } else {
+        static_for<0, R>([&](auto ic) { app[decltype(ic)::value] = 0.0; });
+    }
     static_for<0, R>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         const int j = t + TPF * F::kpos(i);
         const double ej = S.field_zero ? 0.0 : e[i];
         as_global(S.E)[j] = ej;
-        as_global(S.Eeff)[j] = damp == 0.0 ? ej : ej - damp * sin(S.drive_k * (j * S.dx) - dph);
+        as_global(S.Eeff)[j] = ej - app[i];
         e2 = fma(ej, ej, e2);
         finite = finite && isfinite(ej);
     });

@@ -73,7 +73,7 @@ void unit_roots(int n, std::vector<double> &re, std::vector<double> &im) {
 
 struct Layout {
     size_t f, g, E, Eeff, part, rho, mom, tw_x, tw_v, eps_x, eps_v, tw_x64, invk, iden_x, iden_v,
-        feq_g, feq64, ring, dev, total;
+        feq_g, feq64, drv_sc, ring, dev, total;
 };
 
 bool prec_fp64(const vog_config &c) {
@@ -165,6 +165,7 @@ Layout layout_of(const vog_config &c) {
     L.iden_v = take(spline ? es * c.nv : 0);
     L.feq_g = take(es * VOG_MAX_FEQ * c.nv);
     L.feq64 = take(sizeof(double) * c.nv);
+    L.drv_sc = take(c.drive_emax != 0.0 ? 2 * sizeof(double) * c.nx : 0);
     L.ring = take(sizeof(vog_diag) * kRingCap);
     L.dev = take(sizeof(SimDev));
     L.total = off;
@@ -781,6 +782,7 @@ int vog_create(const vog_config *c, void *dev_workspace, size_t bytes, void *hip
     D.iden_v = c->interp == VOG_INTERP_BSPLINE ? s->ws + L.iden_v : nullptr;
     D.interp = c->interp;
     D.invk = (const double *)(s->ws + L.invk);
+    D.drv_sc = c->drive_emax != 0.0 ? (const double *)(s->ws + L.drv_sc) : nullptr;
     D.feq_g = s->ws + L.feq_g;
     D.feq64 = (const double *)(s->ws + L.feq64);
     D.ring = (vog_diag *)(s->ws + L.ring);
@@ -793,7 +795,6 @@ int vog_create(const vog_config *c, void *dev_workspace, size_t bytes, void *hip
     D.nparts = (nv + kTile - 1) / kTile;
     D.poisson = c->poisson;
     D.zero_mean = c->zero_mean;
-    D.drive_k = c->drive_emax != 0.0 ? c->drive_k : 0.0;
     D.fp64 = fp64;
     D.L = c->L;
     D.vmin = c->vmin;
@@ -879,6 +880,15 @@ int vog_create(const vog_config *c, void *dev_workspace, size_t bytes, void *hip
         }
     if ((rc = stage_vec(s, s->ws + L.invk, invk)) != VOG_OK) return bail(rc);
     if ((rc = stage_vec(s, s->ws + L.feq64, s->feq64)) != VOG_OK) return bail(rc);
+    if (c->drive_emax != 0.0) {
+        // E_app(t, x_j) = amp(t) (sin(k x_j) cos(omega t) - cos(k x_j) sin(omega t))
+        std::vector<double> sc(2 * (size_t)nx);
+        for (int j = 0; j < nx; ++j) {
+            sc[2 * j] = sin(c->drive_k * (j * D.dx));
+            sc[2 * j + 1] = cos(c->drive_k * (j * D.dx));
+        }
+        if ((rc = stage_vec(s, s->ws + L.drv_sc, sc)) != VOG_OK) return bail(rc);
+    }
     if ((rc = stage(s, s->ws + L.dev, &D, sizeof(D))) != VOG_OK) return bail(rc);
     *out = s;
     return VOG_OK;
@@ -975,8 +985,13 @@ int vog_set_E(vog_sim *s, const double *host_E) {
     std::vector<double> eff(host_E, host_E + nx);
     double amp, ph;
     drive_at(s->cfg, s->t, &amp, &ph);
-    if (amp != 0.0)
-        for (int i = 0; i < nx; ++i) eff[i] -= amp * sin(s->cfg.drive_k * (i * s->host_dev.dx) - ph);
+    if (amp != 0.0) {  // the form the field solve uses
+        const double cph = cos(ph), sph = sin(ph);
+        for (int i = 0; i < nx; ++i) {
+            const double kx = s->cfg.drive_k * (i * s->host_dev.dx);
+            eff[i] -= amp * (sin(kx) * cph - cos(kx) * sph);
+        }
+    }
     HIP_TRY(hipMemcpyAsync(s->host_dev.E, host_E, sizeof(double) * nx, hipMemcpyHostToDevice, s->stream));
     HIP_TRY(hipMemcpyAsync(s->host_dev.Eeff, eff.data(), sizeof(double) * nx, hipMemcpyHostToDevice, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));

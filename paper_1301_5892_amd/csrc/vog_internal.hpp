@@ -34,9 +34,9 @@ struct SimDev {
     const double *invk;    // [nx] 1 / (nx k_m), k_m = 2 pi mt / L; 0 at m = 0, nx/2 (field solve)
     const void *feq_g;  // [n_feq][nv] component values f_g(v_j), storage precision
     const double *feq64;    // [nv] f_eq(v_j), FP64
+    const double *drv_sc;   // [nx][2] sin(k x_j), cos(k x_j) of the drive wavenumber (else null)
     vog_diag *ring;     // [kRingCap]
     int nx, nv, d, deltaf, field_zero, n_feq, nparts, fp64, poisson, zero_mean, interp;
-    double drive_k;     // wavenumber of the external drive (0: none)
     double L, vmin, dx, dv, inv_dx, inv_dv;
     double feq_c[VOG_MAX_FEQ], feq_inv_s2[VOG_MAX_FEQ];
     double feq_const;   // dv * sum_j f_eq(v_j) (delta f), else 0
