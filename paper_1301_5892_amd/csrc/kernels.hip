@@ -9,12 +9,18 @@
 //  xsweep_fused_kernel
 //                   the x-advection on the v-fastest layout, tiles of whole
 //                   x-lines loaded straight into registers.
+//  sweep_v_mixed_kernel, xsweep_mixed_kernel, field_mixed_kernel
+//                   one launch over sims of different line lengths (batches of
+//                   the serving loop): each block finds its sim and runs the
+//                   body compiled for that sim's length.
 //  transpose_kernel tiled LDS transpose between the v-fastest and x-fastest
 //                   layouts for grids the tiled x-sweep does not cover; the
 //                   x->v direction also emits FP64 partial sums of f over 64
 //                   velocities for rho = int f dv.
 //  field_kernel     FFT (or trapezoidal) Poisson solve in FP64 (Section 3.2),
-//                   E and E - E_app, and the per-step diagnostics record.
+//                   E and E - E_app, and the per-step diagnostics record
+//                   (x-lines of 2048 and 4096 points; shorter ones go through
+//                   field_mixed_kernel).
 //  rho_v_kernel     rho = int f dv from the v-fastest layout; moments
 //                   kernels, init and fill helpers.
 #include "fft.hpp"
