@@ -440,3 +440,29 @@ def test_mixed_lengths_more_sims_than_one_launch(gpu):
     vog.step_batch(sims, 4)
     for s, f0 in zip(sims[:4] + sims[-4:], alone):
         assert np.array_equal(s.get_raw(), f0)
+
+
+def test_mixed_lengths_with_merged_and_driven_sims(gpu):
+    # A batch that mixes line lengths, merged v half-steps, a KEEN-driven sim,
+    # FP64 sims (their own kernels) and nx < 64 (transposed x-sweep): each
+    # sim equals the same sim stepped alone, over two calls.
+    from paper_1301_5892_amd import vog
+    base = workloads.landau_weak()
+    ws = [merged(base.replace(nx=256, nv=512, precision="fp32_deltaf")),
+          base.replace(nx=128, nv=1024, precision="fp32_deltaf"),
+          workloads.keen(128, 0.1, 20).replace(nv=256),
+          base.replace(nx=512, nv=128, precision="fp64_plain"),
+          base.replace(nx=32, nv=256, precision="fp32_deltaf"),
+          merged(base.replace(nx=64, nv=2048, precision="fp32_plain"))]
+    alone = []
+    for w in ws:
+        s = gpu.Sim(w).init()
+        s.step(5)
+        s.step(4)
+        alone.append((s.get_raw(), s.get_E()))
+    sims = [gpu.Sim(w).init() for w in ws]
+    vog.step_batch(sims, 5)
+    vog.step_batch(sims, 4)
+    for w, s, (f0, e0) in zip(ws, sims, alone):
+        assert np.array_equal(s.get_raw(), f0), w.name
+        assert np.array_equal(s.get_E(), e0), w.name
