@@ -218,6 +218,16 @@ int vog_get_time(const vog_sim *sim, int64_t *step, double *t);
  * recorded field was not finite. */
 int vog_sync(vog_sim *sim);
 
+/* vog_sync for several sims that share one device and stream (a batch of
+ * vog_step_batch): waits for the stream once and sets status[k] to VOG_OK or
+ * VOG_ENONFINITE for sims[k], read from every sim's last diagnostics record
+ * with one gather launch and one copy per up to 64 sims.  status: host
+ * array of nsims ints, written on success.  The gather uses a small device
+ * buffer the library allocates once per device; calls on one device are
+ * serialised.  VOG_EINVAL for a NULL argument, nsims < 1 or sims that do not
+ * share the device and stream. */
+int vog_sync_batch(vog_sim *const *sims, int nsims, int *status);
+
 void vog_destroy(vog_sim *sim);
 
 const char *vog_strerror(int code);

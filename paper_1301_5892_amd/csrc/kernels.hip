@@ -1150,6 +1150,23 @@ void launch_init(bool fp64, const SimDev *s, int cells, int nmodes, const double
     else hipLaunchKernelGGL((init_kernel<float>), dim3(blocks), dim3(256), 0, st, s, a);
 }
 
+__global__ __launch_bounds__(64) void finite_gather_kernel(const Batch b, int *out) {
+    const int k = (int)threadIdx.x;
+    if (k >= b.n) return;
+    const SimDev &S = *b.s[k];
+    const int64_t st = b.step[k];
+    int ok = 1;
+    if (st > 0 && !S.field_zero) {
+        const vog_diag &d = S.ring[st % kRingCap];
+        if (d.step == st && !d.finite) ok = 0;
+    }
+    out[k] = ok;
+}
+
+void launch_finite_gather(const Batch &b, int *out, hipStream_t st) {
+    hipLaunchKernelGGL(finite_gather_kernel, dim3(1), dim3(64), 0, st, b, out);
+}
+
 __global__ __launch_bounds__(256) void fill_kernel(uint32_t *p, size_t nwords) {
     for (size_t k = blockIdx.x * (size_t)256 + threadIdx.x; k < nwords; k += (size_t)gridDim.x * 256)
         p[k] = 0u;

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1122,6 +1123,46 @@ int vog_sync(vog_sim *s) {
         vog_diag d;
         HIP_TRY(hipMemcpy(&d, s->host_dev.ring + (s->step % kRingCap), sizeof(d), hipMemcpyDeviceToHost));
         if (d.step == s->step && !d.finite) return fail(VOG_ENONFINITE, "field is not finite");
+    }
+    return VOG_OK;
+}
+
+int vog_sync_batch(vog_sim *const *sims, int nsims, int *status) {
+    if (!sims || nsims < 1 || !status) return fail(VOG_EINVAL, "NULL argument or nsims < 1");
+    for (int k = 0; k < nsims; ++k) {
+        if (!sims[k]) return fail(VOG_EINVAL, "sim is NULL");
+        if (sims[k]->device != sims[0]->device || sims[k]->stream != sims[0]->stream)
+            return fail(VOG_EINVAL, "sims of a batch must share the device and stream");
+    }
+    vog_sim *lead = sims[0];
+    int rc = device_guard(lead);
+    if (rc != VOG_OK) return rc;
+    // one flag buffer of kMaxBatch ints per device, kept for the process
+    static std::mutex mu;
+    static std::map<int, int *> bufs;
+    std::lock_guard<std::mutex> g(mu);
+    int *&flags = bufs[lead->device];
+    if (!flags && hipMalloc((void **)&flags, sizeof(int) * kMaxBatch) != hipSuccess) {
+        flags = nullptr;
+        return fail(VOG_ENOMEM, "flag buffer allocation failed");
+    }
+    std::vector<int> host(nsims, 1);
+    for (int base = 0; base < nsims; base += kMaxBatch) {
+        Batch b{};
+        b.n = std::min(kMaxBatch, nsims - base);
+        for (int k = 0; k < b.n; ++k) {
+            b.s[k] = sims[base + k]->dev;
+            b.step[k] = sims[base + k]->step;
+        }
+        launch_finite_gather(b, flags, lead->stream);
+        if ((rc = check_launch()) != VOG_OK) return rc;
+        HIP_TRY(hipMemcpyAsync(host.data() + base, flags, sizeof(int) * b.n, hipMemcpyDeviceToHost,
+                               lead->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(lead->stream));
+    for (int k = 0; k < nsims; ++k) {
+        sims[k]->staging.clear();
+        status[k] = host[k] ? VOG_OK : VOG_ENONFINITE;
     }
     return VOG_OK;
 }

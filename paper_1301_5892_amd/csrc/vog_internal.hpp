@@ -90,5 +90,8 @@ void launch_moments(bool fp64, const Batch &b, int max_nx, hipStream_t st);
 void launch_init(bool fp64, const SimDev *s, int cells, int nmodes, const double *amp,
                  const double *kx, const double *ph, hipStream_t st);
 void launch_fill(void *p, size_t bytes, hipStream_t st);
+// out[k] = 0 if sim k's diagnostics record of step b.step[k] says its field
+// is not finite, else 1 (k < b.n).
+void launch_finite_gather(const Batch &b, int *out, hipStream_t st);
 
 }  // namespace vog

@@ -150,14 +150,26 @@ class Scheduler:
             self.stats["quanta"] += 1
             check = self.stats["quanta"] % self.check_every == 0
             tq = now()
-            still: List[_Active] = []
             for a, c in zip(active, counts):
                 a.remaining -= c
+            # non-finite checks: every check_every quanta and at completion,
+            # one call for all of them when the executor offers it
+            probe = [a for a in active if a.req.rid not in self.cancelled
+                     and (a.remaining == 0 or check)]
+            bad = set()
+            if probe:
+                if hasattr(self.ex, "failed_many"):
+                    flags = self.ex.failed_many([a.handle for a in probe])
+                else:
+                    flags = [self.ex.failed(a.handle) for a in probe]
+                bad = {id(a) for a, f in zip(probe, flags) if f}
+            still: List[_Active] = []
+            for a in active:
                 rid = a.req.rid
                 w = a.req.workload
                 if rid in self.cancelled:
                     status = "cancelled"
-                elif (a.remaining == 0 or check) and self.ex.failed(a.handle):
+                elif id(a) in bad:
                     status = "failed"
                 elif a.remaining == 0:
                     status = "done"
@@ -225,6 +237,9 @@ class GpuExecutor:
             if e.code == self.vog.ENONFINITE:
                 return True
             raise
+
+    def failed_many(self, handles) -> List[bool]:
+        return [not ok for ok in self.vog.sync_batch(handles)]
 
     def finish(self, h):
         """Result of a finished request: the final field and step count; the

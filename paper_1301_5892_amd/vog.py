@@ -69,7 +69,7 @@ assert DIAG_DTYPE.itemsize == ctypes.sizeof(Diag)
 EXPORTS = ["vog_config_default", "vog_config_validate", "vog_workspace_bytes", "vog_create",
            "vog_init_perturbed", "vog_set_f", "vog_get_f", "vog_get_raw", "vog_get_E",
            "vog_set_E", "vog_step", "vog_step_batch", "vog_sweep", "vog_get_diag",
-           "vog_state_bytes", "vog_get_state", "vog_set_state", "vog_get_time", "vog_sync",
+           "vog_state_bytes", "vog_get_state", "vog_set_state", "vog_get_time", "vog_sync", "vog_sync_batch",
            "vog_destroy", "vog_strerror", "vog_last_error", "vog_profile_enable",
            "vog_profile_read", "vog_build_info"]
 
@@ -110,6 +110,7 @@ def load() -> ctypes.CDLL:
         "vog_get_time": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64),
                                         ctypes.POINTER(ctypes.c_double)]),
         "vog_sync": (ctypes.c_int, [_P]),
+        "vog_sync_batch": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
         "vog_destroy": (None, [_P]),
         "vog_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "vog_last_error": (ctypes.c_char_p, []),
@@ -302,6 +303,16 @@ def step_batch(sims: Sequence[Sim], nsteps: int, dts: Optional[Sequence[float]] 
     arr = (_P * n)(*[s.handle for s in sims])
     dt = np.ascontiguousarray([s.w.dt for s in sims] if dts is None else dts, dtype=np.float64)
     _check(load().vog_step_batch(arr, n, _dp(dt), int(nsteps)), "vog_step_batch")
+
+
+def sync_batch(sims: Sequence[Sim]) -> List[bool]:
+    """Waits for the shared stream once; whether each sim's last recorded
+    field is finite."""
+    n = len(sims)
+    arr = (_P * n)(*[s.handle for s in sims])
+    st = (ctypes.c_int * n)()
+    _check(load().vog_sync_batch(arr, n, st), "vog_sync_batch")
+    return [st[k] == OK for k in range(n)]
 
 
 def build_info() -> str:

@@ -63,3 +63,42 @@ def test_serving_summary(gpu):
     assert s["done"] == 16
     assert 0 < s["p50_latency_s"] <= s["p99_latency_s"]
     assert s["aggregate_cell_updates_per_s"] > 0
+
+
+def test_sync_batch_flags_only_the_diverged_sim(gpu):
+    # 70 sims (two gather launches of at most 64); sim 66 gets a NaN in f.
+    from paper_1301_5892_amd import vog
+    base = workloads.landau_weak()
+    sims = [vog.Sim(base.replace(nx=64, nv=128, amp=(0.01 + 1e-4 * i,))).init() for i in range(70)]
+    assert vog.sync_batch(sims) == [True] * 70            # step 0: nothing recorded yet
+    f = sims[66].get_f()
+    f[3, 5] = float("nan")
+    sims[66].set_f(f)
+    vog.step_batch(sims, 2)
+    ok = vog.sync_batch(sims)
+    assert ok == [k != 66 for k in range(70)]
+    for k in (0, 63, 64, 66, 69):                          # the single-sim call agrees
+        if k == 66:
+            with pytest.raises(vog.VogError):
+                sims[k].sync()
+        else:
+            sims[k].sync()
+
+
+def test_sync_batch_rejects_bad_arguments(gpu):
+    import ctypes
+
+    import torch
+
+    from paper_1301_5892_amd import vog
+    L = vog.load()
+    a = vog.Sim(workloads.landau_weak()).init()
+    st = (ctypes.c_int * 2)()
+    one = (vog._P * 1)(a.handle)
+    assert L.vog_sync_batch(one, 0, st) == vog.EINVAL
+    assert L.vog_sync_batch(one, 1, None) == vog.EINVAL
+    other = torch.cuda.Stream()
+    b = vog.Sim(workloads.landau_weak(), stream=other).init()
+    two = (vog._P * 2)(a.handle, b.handle)
+    assert L.vog_sync_batch(two, 2, st) == vog.EINVAL     # different streams
+    torch.cuda.synchronize()

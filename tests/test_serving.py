@@ -1,8 +1,9 @@
 """Host logic of the continuous-batching scheduler, with a fake executor on a
 virtual clock (no GPU): admission by footprint, arrival order, queueing,
 cancellation, failure isolation, rejection, latency accounting.  Each test
-runs with an executor that only advances whole quanta and with one that
-launches a quantum and waits for it separately (admission overlaps it)."""
+runs with an executor that only advances whole quanta and checks sims one by
+one, and with one that launches a quantum and waits for it separately
+(admission overlaps it) and checks sims in one call."""
 import dataclasses
 
 import pytest
@@ -93,6 +94,10 @@ class FakeOverlapExecutor(FakeExecutor):
 
     def advance(self, handles, counts):
         raise AssertionError("the overlapping executor is driven by launch/wait")
+
+    def failed_many(self, handles):
+        assert self.queued is None
+        return [self.failed(h) for h in handles]
 
 
 @pytest.fixture(params=[FakeExecutor, FakeOverlapExecutor], ids=["advance", "overlap"])
