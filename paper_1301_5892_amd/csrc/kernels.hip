@@ -121,6 +121,44 @@ __device__ __forceinline__ const gmem<T> *as_global(const T *p) { return (const 
 template <>
 __device__ __forceinline__ float fma_t<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
+// Raw buffer access: a descriptor with the base address in scalar registers
+// and 32-bit byte offsets per lane (voff) and per instruction (soff), so an
+// access needs no 64-bit address arithmetic.  Accesses at or past `bytes`
+// read 0 and drop the store.  Word 3 of the descriptor selects the 32-bit
+// data format of the gfx9 family.
+constexpr int kBufWord3 = 0x00020000;
+
+// base and bytes must be the same in every lane of the wave (they are taken
+// from the first active lane, so that the descriptor lives in scalar
+// registers and the compiler emits no per-lane loop around the accesses).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void *base, unsigned bytes) {
+    // (readfirstlane works on int: widen through unsigned, never sign-extend)
+    const uint64_t a = (uint64_t)base;
+    const uint64_t hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(a >> 32));
+    const uint64_t lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)a);
+    const uint64_t u = (hi << 32) | lo;
+    return __builtin_amdgcn_make_buffer_rsrc((void *)u, 0, (int)__builtin_amdgcn_readfirstlane(bytes),
+                                             kBufWord3);
+}
+
+template <typename T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    if constexpr (sizeof(T) == 4)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+
+template <typename T>
+__device__ __forceinline__ void buf_store(T x, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    if constexpr (sizeof(T) == 4) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, voff, soff, 0);
+    } else {
+        using U = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U, x), r, voff, soff, 0);
+    }
+}
+
 // ----------------------------------------------------------------- sweep
 
 // delta-f source of one line along the thread's output positions
@@ -133,9 +171,10 @@ __device__ __forceinline__ float fma_t<float>(float a, float b, float c) { retur
 //   expm1(y + d) = expm1(y) + expm1(d) (1 + expm1(y)),  d = A_g TPF dv.
 template <typename T, int N, int R, int TPF>
 __device__ __forceinline__ void deltaf_source(const SimDev &S, double tauE, int p0,
-                                              T (&src)[R]) {
+                                              const unsigned (&pos)[R], T (&src)[R]) {
     static_for<0, R>([&](auto kc) { src[decltype(kc)::value] = (T)0; });
-    const gmem<T> *fg = as_global((const T *)S.feq_g);
+    // table rows f_g(v_j), N values each; pos[k] = byte offset of pos_k in a row
+    const __amdgpu_buffer_rsrc_t fg = buf_rsrc(S.feq_g, (unsigned)(S.n_feq * N * sizeof(T)));
     const T vmin = (T)S.vmin, dv = (T)S.dv;
     const int kw = (N - p0 + TPF - 1) / TPF;  // first wrapped k (R when none)
     const int pw = p0 + kw * TPF - N;         // its position
@@ -145,7 +184,7 @@ __device__ __forceinline__ void deltaf_source(const SimDev &S, double tauE, int 
         const T A = (T)A64;
         const T C = (T)(-A64 * S.feq_c[g] - 0.5 * tauE * tauE * is2);
         const T rm1 = expm1_t<T>((T)(A64 * (double)TPF * S.dv));
-        const gmem<T> *row = fg + g * N;
+        const unsigned row = (unsigned)(g * N * sizeof(T));
         const T e0 = expm1_t<T>(fma_t<T>(A, vmin + (T)p0 * dv, C));
         const T ew = expm1_t<T>(fma_t<T>(A, vmin + (T)(kw < R ? pw : 0) * dv, C));
         T e = e0;
@@ -155,7 +194,7 @@ __device__ __forceinline__ void deltaf_source(const SimDev &S, double tauE, int 
                 const T er = e + fma_t<T>(rm1, e, rm1);
                 e = k == kw ? ew : er;
             }
-            src[k] = fma_t<T>(row[(p0 + k * TPF) & (N - 1)], e, src[k]);
+            src[k] = fma_t<T>(buf_load<T>(fg, pos[k], row), e, src[k]);
         });
     }
 }
@@ -333,9 +372,21 @@ __device__ __forceinline__ void sweep_body(const Batch &b, int sim, int blk, T *
     T *lim = lds[slot][1];
     const cx<T> *tw = (const cx<T> *)(KIND == 0 ? S.tw_v : S.tw_x);
     const cx<T> *eps = (const cx<T> *)(KIND == 0 ? S.eps_v : S.eps_x) + t * kEpsRow;
-    T *data = (T *)(KIND == 0 ? S.f : S.g);
-    gmem<T> *pA = as_global(data + (size_t)lineA * N);
-    gmem<T> *pB = as_global(data + (size_t)lineB * N);
+    // One pair per block: a descriptor per line (uniform base).  Otherwise one
+    // for the sim's array, with the line's offset in the byte offset.
+    constexpr unsigned LB = N * sizeof(T);  // bytes per line
+    const T *data = (const T *)(KIND == 0 ? S.f : S.g);
+    __amdgpu_buffer_rsrc_t rA, rB;
+    unsigned oA, oB;
+    if constexpr (PPB == 1) {
+        rA = buf_rsrc(data + (size_t)lineA * N, LB);  // slot 0 for every thread
+        rB = buf_rsrc(data + (size_t)lineB * N, LB);
+        oA = oB = 0;
+    } else {
+        rA = rB = buf_rsrc(data, (unsigned)nlines * LB);
+        oA = (unsigned)lineA * LB;
+        oB = oA + LB;
+    }
 
     // Shift of each line, FP64: v-sweep beta = -tau E_i / dv, x-sweep
     // beta = -v_j dt / dx.
@@ -359,11 +410,14 @@ __device__ __forceinline__ void sweep_body(const Batch &b, int sim, int blk, T *
     // Load the two lines packed as z = uA + i uB (a slot past the last pair
     // reads lines 0 and 1 and stores nothing).
     cx<T> v[R];
-    static_for<0, R>([&](auto rc) {
-        constexpr int r = decltype(rc)::value;
-        const int j = t + r * TPF;
-        v[r] = cx<T>{pA[j], pB[j]};
-    });
+    {
+        const unsigned tb = (unsigned)t * sizeof(T);
+        static_for<0, R>([&](auto rc) {
+            constexpr unsigned r = decltype(rc)::value;
+            v[r] = cx<T>{buf_load<T>(rA, oA + tb, r * TPF * sizeof(T)),
+                         buf_load<T>(rB, oB + tb, r * TPF * sizeof(T))};
+        });
+    }
 
     cx<T> Y[R];
     pair_transform<T, N, (sizeof(T) == 8)>(v, Y, t, lre, lim, tw, eps, wsh[slot][0], wsh[slot][1],
@@ -371,30 +425,45 @@ __device__ __forceinline__ void sweep_body(const Batch &b, int sim, int blk, T *
 
     if (!active) return;
 
-    // Store: unshifted index j goes to line position (j - b) mod N.
+    // Store: unshifted index j goes to line position (j - b) mod N; pos[k] is
+    // the byte offset of position (p0 + k TPF) mod N in a line.
     const int p0A = (t - (int)(bA & (N - 1))) & (N - 1);
     const int p0B = (t - (int)(bB & (N - 1))) & (N - 1);
+    auto positions = [&](int p0, unsigned (&pos)[R]) {
+        const unsigned p = (unsigned)p0 * sizeof(T);
+        static_for<0, R>([&](auto kc) {
+            constexpr unsigned k = decltype(kc)::value;
+            pos[k] = (p + k * TPF * sizeof(T)) & (LB - 1);
+        });
+    };
+    unsigned pos[R];
     if constexpr (KIND == 0) {
         if (S.deltaf) {
             T src[R];
-            deltaf_source<T, N, R, TPF>(S, arg * EA, p0A, src);
+            positions(p0A, pos);
+            deltaf_source<T, N, R, TPF>(S, arg * EA, p0A, pos, src);
             static_for<0, R>([&](auto kc) {
                 constexpr int k = decltype(kc)::value;
-                pA[(p0A + k * TPF) & (N - 1)] = Y[F::kinv(k)].re + src[k];
+                buf_store<T>(Y[F::kinv(k)].re + src[k], rA, oA + pos[k], 0);
             });
-            deltaf_source<T, N, R, TPF>(S, arg * EB, p0B, src);
+            positions(p0B, pos);
+            deltaf_source<T, N, R, TPF>(S, arg * EB, p0B, pos, src);
             static_for<0, R>([&](auto kc) {
                 constexpr int k = decltype(kc)::value;
-                pB[(p0B + k * TPF) & (N - 1)] = Y[F::kinv(k)].im + src[k];
+                buf_store<T>(Y[F::kinv(k)].im + src[k], rB, oB + pos[k], 0);
             });
             return;
         }
     }
+    positions(p0A, pos);
     static_for<0, R>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
-        constexpr int i = F::kinv(k);
-        pA[(p0A + k * TPF) & (N - 1)] = Y[i].re;
-        pB[(p0B + k * TPF) & (N - 1)] = Y[i].im;
+        buf_store<T>(Y[F::kinv(k)].re, rA, oA + pos[k], 0);
+    });
+    positions(p0B, pos);
+    static_for<0, R>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        buf_store<T>(Y[F::kinv(k)].im, rB, oB + pos[k], 0);
     });
 }
 
