@@ -112,6 +112,10 @@ def test_null_arguments_fail_cleanly(vog):
     assert L.vog_create(None, None, 0, None, ctypes.byref(out)) == vog.EINVAL
     assert L.vog_step(None, 0.1, 1) == vog.EINVAL
     assert L.vog_sync(None) == vog.EINVAL
+    st = (ctypes.c_int * 1)()
+    assert L.vog_sync_batch(None, 1, st) == vog.EINVAL
+    assert L.vog_sync_batch((vog._P * 1)(None), 1, st) == vog.EINVAL
+    assert L.vog_sync_batch((vog._P * 1)(None), 0, st) == vog.EINVAL
     L.vog_destroy(None)
     assert L.vog_strerror(vog.ENONFINITE) == b"non-finite field"
 
