@@ -158,6 +158,21 @@ __device__ __forceinline__ void load_row(const cx<T> *__restrict__ row, cx<T> (&
     }
 }
 
+// Synchronisation of the threads of one transform around an LDS exchange.
+// WAVE: they are contiguous lanes of a single wave, which executes its LDS
+// operations in order, so ordering the wave's own accesses is enough;
+// otherwise the whole block waits.
+template <bool WAVE>
+__device__ __forceinline__ void xsync() {
+    if constexpr (WAVE) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 template <typename T, int N>
 struct Fft {
     static_assert(N >= 8 && N <= 4096 && (N & (N - 1)) == 0, "N must be a power of two in [8, 4096]");
@@ -203,11 +218,12 @@ struct Fft {
     }
 
     // Stockham exchange after pass P: store in autosort order, reload in the
-    // layout of pass P + 1.  All threads of the block must call it.
-    template <int P>
+    // layout of pass P + 1.  All threads of the block must call it (WAVE: all
+    // threads of the wave; see xsync).
+    template <int P, bool WAVE = false>
     static __device__ __forceinline__ void exchange(cx<T> (&v)[R], int t, T *lre, T *lim) {
         constexpr int RP = radix(P), NS = ns(P), RQ = radix(P + 1);
-        __syncthreads();
+        xsync<WAVE>();
         static_for<0, R / RP>([&](auto uc) {
             constexpr int u = decltype(uc)::value;
             const int jb = t + u * TPF;
@@ -223,7 +239,7 @@ struct Fft {
                 lim[idx] = v[u * RP + r].im;
             });
         });
-        __syncthreads();
+        xsync<WAVE>();
         const int pt = pad(t);
         static_for<0, R / RQ>([&](auto uc) {
             constexpr int u = decltype(uc)::value;
@@ -239,13 +255,13 @@ struct Fft {
     }
 
     // Full transform: X_m = sum_n x_n exp(DIR 2 pi i n m / N), unnormalised.
-    template <int DIR>
+    template <int DIR, bool WAVE = false>
     static __device__ __forceinline__ void run(cx<T> (&v)[R], int t, T *lre, T *lim,
                                                const cx<T> *__restrict__ tw) {
         static_for<0, NPASS>([&](auto pc) {
             constexpr int p = decltype(pc)::value;
             pass<DIR, p>(v, t, tw);
-            if constexpr (p + 1 < NPASS) exchange<p>(v, t, lre, lim);
+            if constexpr (p + 1 < NPASS) exchange<p, WAVE>(v, t, lre, lim);
         });
     }
 

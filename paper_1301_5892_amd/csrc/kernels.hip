@@ -225,8 +225,9 @@ __device__ __forceinline__ void pair_weights(int d, int interp, double sA, doubl
 // evaluated for the combined weights wP and wQ.  For B-splines (iden not
 // null) the packed product of mode m is divided by the collocation symbol:
 // Y_m *= iden[m].  All threads of the block must call this (it contains
-// block barriers).
-template <typename T, int N, bool RELOAD_TW, int R = fft_regs(N)>
+// block barriers); WAVE: the pair's threads are contiguous lanes of one wave,
+// and only that wave's threads must call it together.
+template <typename T, int N, bool RELOAD_TW, bool WAVE = false, int R = fft_regs(N)>
 __device__ __forceinline__ void pair_transform(cx<T> (&v)[R], cx<T> (&Y)[R], int t, T *lre, T *lim,
                                                const cx<T> *__restrict__ tw,
                                                const cx<T> *eps,
@@ -236,7 +237,7 @@ __device__ __forceinline__ void pair_transform(cx<T> (&v)[R], cx<T> (&Y)[R], int
     constexpr int TPF = F::TPF;
     static_assert(R == F::R, "register count");
 
-    F::template run<-1>(v, t, lre, lim, tw);  // v[i] = Z[t + TPF kpos(i)]
+    F::template run<-1, WAVE>(v, t, lre, lim, tw);  // v[i] = Z[t + TPF kpos(i)]
 
     auto symbol = [&](const T *w, cx<T>(&H)[R]) {
         cx<T> e[kEpsRow];
@@ -263,7 +264,7 @@ __device__ __forceinline__ void pair_transform(cx<T> (&v)[R], cx<T> (&Y)[R], int
 
     if constexpr (TPF > 1) {
         // Z to LDS at its natural position for the partner exchange.
-        __syncthreads();
+        xsync<WAVE>();
         const int pt = F::pad(t);
         static_for<0, R>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
@@ -281,7 +282,7 @@ __device__ __forceinline__ void pair_transform(cx<T> (&v)[R], cx<T> (&Y)[R], int
                 Y[k] = cmul(H[k], v[i]);
             });
         }
-        __syncthreads();
+        xsync<WAVE>();
         {
             cx<T> H[R];
             symbol(wQ, H);
@@ -300,7 +301,7 @@ __device__ __forceinline__ void pair_transform(cx<T> (&v)[R], cx<T> (&Y)[R], int
             });
         }
     } else {
-        __syncthreads();  // weights visible
+        xsync<WAVE>();  // weights visible
         cx<T> H[R];
         symbol(wP, H);
         static_for<0, R>([&](auto ic) {
@@ -327,8 +328,8 @@ __device__ __forceinline__ void pair_transform(cx<T> (&v)[R], cx<T> (&Y)[R], int
 
     // RELOAD_TW: re-read the twiddle rows instead of keeping the forward
     // pass's rows live in registers (for kernels with a tight register budget).
-    if constexpr (RELOAD_TW) F::template run<1>(Y, t, lre, lim, opaque(tw));
-    else F::template run<1>(Y, t, lre, lim, tw);  // Y[i] = y[t + TPF kpos(i)]
+    if constexpr (RELOAD_TW) F::template run<1, WAVE>(Y, t, lre, lim, opaque(tw));
+    else F::template run<1, WAVE>(Y, t, lre, lim, tw);  // Y[i] = y[t + TPF kpos(i)]
 }
 
 // KIND 0: v-advection by tau = b.a[sim] with field E (lines are x-columns of
@@ -420,8 +421,10 @@ __device__ __forceinline__ void sweep_body(const Batch &b, int sim, int blk, T *
     }
 
     cx<T> Y[R];
-    pair_transform<T, N, (sizeof(T) == 8)>(v, Y, t, lre, lim, tw, eps, wsh[slot][0], wsh[slot][1],
-                                           (const T *)(KIND == 0 ? S.iden_v : S.iden_x));
+    // a line pair of at most 1024 points is one wave's contiguous lanes
+    pair_transform<T, N, (sizeof(T) == 8), (TPF <= 64)>(
+        v, Y, t, lre, lim, tw, eps, wsh[slot][0], wsh[slot][1],
+        (const T *)(KIND == 0 ? S.iden_v : S.iden_x));
 
     if (!active) return;
 
