@@ -186,10 +186,12 @@ int vog_set_E(vog_sim *sim, const double *host_E);
  * returns after enqueueing.  dt > 0 and finite, nsteps >= 0 (0: no-op). */
 int vog_step(vog_sim *sim, double dt, int nsteps);
 
-/* nsteps Strang steps for nsims sims at once, sim k with step dt[k], with one
- * grouped launch per kernel type and line length.  Every sim must use the
- * stream of sims[0], and no sim may appear twice.  Each sim's result is
- * bitwise identical to vog_step on that sim alone. */
+/* nsteps Strang steps for nsims sims at once, sim k with step dt[k], with
+ * grouped launches of up to 64 sims: one per kernel type and line length, and
+ * for FP32 sims one per sweep covering all their line lengths (v-lines of
+ * 64..4096 points, x-lines of 64..1024).  Every sim must use the stream of
+ * sims[0], and no sim may appear twice.  Each sim's result is bitwise
+ * identical to vog_step on that sim alone. */
 int vog_step_batch(vog_sim *const *sims, int nsims, const double *dt, int nsteps);
 
 /* Single sweeps, for testing the pieces of the step on their own:
