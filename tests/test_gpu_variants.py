@@ -391,7 +391,9 @@ def _mixed_fp32():
             base.replace(nx=512, nv=512, precision="fp32_deltaf"),
             base.replace(nx=64, nv=128, precision="fp32_plain"),
             spline(base.replace(nx=128, nv=1024, precision="fp32_deltaf"), 5),
-            base.replace(nx=32, nv=64, precision="fp32_deltaf")]
+            base.replace(nx=32, nv=64, precision="fp32_deltaf"),
+            # v-lines of 32 points: their own launch beside the mixed one
+            base.replace(nx=64, nv=32, precision="fp32_deltaf")]
 
 
 def test_mixed_lengths_batch_equals_alone(gpu):
