@@ -273,6 +273,65 @@ def test_landau_mass_and_field_history(orc):
     assert np.all(d[:, 0] > 0) and d[-1, 0] < d[0, 0]        # damping
 
 
+# ------------------------------------------------------------------ diagnostics
+
+def _wide_landau(alpha=0.01):
+    # Weak Landau data on a velocity box wide enough (|v| <= 10, tail of
+    # f_M below 1e-22) that the rectangle rule integrates the Gaussian
+    # moments to FP64 round-off.
+    return workloads.landau_weak().replace(name="landau_wide_64x256", nv=256, vmin=-10.0,
+                                           vmax=10.0, amp=(alpha,))
+
+
+@pytest.mark.parametrize("deltaf", [False, True])
+def test_diag_field_closed_form_at_t0(orc, deltaf):
+    # f0 = (1 + a cos kx) f_M with k = 2 pi / L: rho = 1 + a cos kx, so
+    # E = (a/k) sin kx and (Sections 4.1, 4.3)
+    #   ||E||_2 = (dx sum E_i^2)^(1/2) = (a/k) (L/2)^(1/2),
+    #   rho_hat_0 = mean rho = 1,   |rho_hat_1| = a/2.
+    a, k = 0.01, 0.5
+    w = _wide_landau(a)
+    o = orc.Oracle(w, deltaf=deltaf).init()
+    normE, rho0, rho1 = o.diag_field()
+    assert abs(normE - (a / k) * math.sqrt(w.L / 2)) < 1e-14
+    assert abs(rho0 - 1.0) < 1e-14
+    assert abs(rho1 - a / 2) < 1e-15
+
+
+@pytest.mark.parametrize("deltaf", [False, True])
+@pytest.mark.parametrize("a", [0.01, 0.5])
+def test_diag_moments_closed_form_at_t0(orc, deltaf, a):
+    # Same f0 (Section 4.2 definitions, f_M = exp(-v^2/2)/sqrt(2 pi)):
+    #   L2 = int int f^2 = L (1 + a^2/2) int f_M^2 dv = L (1 + a^2/2) / (2 sqrt(pi)),
+    #   energy = 1/2 int int f v^2 + 1/2 int E^2 = L/2 + (a/k)^2 L/4.
+    k = 0.5
+    w = _wide_landau(a)
+    o = orc.Oracle(w, deltaf=deltaf).init()
+    l2, energy = o.diag_moments()
+    assert abs(l2 - w.L * (1 + a * a / 2) / (2 * math.sqrt(math.pi))) < 1e-13
+    assert abs(energy - (w.L / 2 + (a / k) ** 2 * w.L / 4)) < 1e-13
+
+
+@pytest.mark.parametrize("deltaf", [False, True])
+def test_energy_conserved_while_field_energy_moves(orc, deltaf):
+    # Vlasov-Poisson conserves the total energy; the split semi-Lagrangian
+    # step keeps it up to the O(dt^2) splitting and interpolation errors.
+    # Over 50 steps the electric energy swings by ~1e-3 (Landau damping moves
+    # it into kinetic energy); the total moves by less than 1% of that swing,
+    # so a wrong factor on either term would show.
+    w = _wide_landau(0.01)
+    o = orc.Oracle(w, deltaf=deltaf).init()
+    e0 = o.diag_moments()[1]
+    ee0 = 0.5 * o.dx * np.sum(o.E ** 2)
+    drift, swing = 0.0, 0.0
+    for _ in range(10):
+        o.step(5)
+        drift = max(drift, abs(o.diag_moments()[1] - e0))
+        swing = max(swing, abs(0.5 * o.dx * np.sum(o.E ** 2) - ee0))
+    assert swing > 5e-4
+    assert drift < 0.01 * swing, (drift, swing)
+
+
 # ------------------------------------------------------------------ variants
 
 def _trap(w, zero_mean=True):
