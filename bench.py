@@ -70,7 +70,8 @@ def kernel_source_hash() -> str:
     that an edit of the comments alone keeps a counter measurement valid."""
     import re
     h = hashlib.sha256()
-    for name in ("fft.hpp", "kernels.hip", "vog_internal.hpp"):
+    for name in ("fft.hpp", "kernels.hpp", "sweep_f32.hip", "sweep_f64.hip", "xsweep.hip",
+                 "mixed.hip", "field.hip", "misc.hip", "vog_internal.hpp"):
         with open(os.path.join(ROOT, "paper_1301_5892_amd", "csrc", name)) as fh:
             text = fh.read()
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)

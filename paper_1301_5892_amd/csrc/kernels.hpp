@@ -1,4 +1,7 @@
-// HIP kernels of the split step (gfx950, wave64).
+#pragma once
+// Device code of the split step (gfx950, wave64), shared by the kernel
+// translation units sweep_f32.hip, sweep_f64.hip, xsweep.hip, mixed.hip,
+// field.hip and misc.hip (which instantiate the kernels and their launchers).
 //
 //  sweep_kernel     one constant advection (Section 1.2) for a batch of lines:
 //                   forward FFT of two real lines packed as one complex line,
@@ -23,13 +26,13 @@
 //                   field_mixed_kernel).
 //  rho_v_kernel     rho = int f dv from the v-fastest layout; moments
 //                   kernels, init and fill helpers.
+
 #include "fft.hpp"
 #include "vog_internal.hpp"
 
 #include <math.h>
 
 namespace vog {
-
 // ----------------------------------------------------------------- helpers
 
 // Lagrange 2d+1 coefficient of node q for the fractional shift s in [0, 1)
@@ -488,26 +491,6 @@ __device__ __forceinline__ int mixed_sim(const Batch &b, const BlockMap &m, int 
     return __builtin_amdgcn_readfirstlane(__popcll(__ballot(le)));
 }
 
-// FP32 v-sweeps of sims with lines of 64 .. 4096 points in one launch: every
-// block runs the body of its sim's line length (each block carries 8192
-// values whatever the length).
-__global__ __launch_bounds__(256, 3) void sweep_v_mixed_kernel(const Batch b, const BlockMap m) {
-    __shared__ float smem[Sweep<float, 64>::SMEM];  // the largest of 64 .. 4096
-    const int bid = (int)blockIdx.x;
-    const int k = mixed_sim(b, m, bid);
-    const int blk = bid - m.first[k];
-    switch (m.lgn[k]) {
-    case 6: sweep_body<float, 64, 0>(b, k, blk, smem); break;
-    case 7: sweep_body<float, 128, 0>(b, k, blk, smem); break;
-    case 8: sweep_body<float, 256, 0>(b, k, blk, smem); break;
-    case 9: sweep_body<float, 512, 0>(b, k, blk, smem); break;
-    case 10: sweep_body<float, 1024, 0>(b, k, blk, smem); break;
-    case 11: sweep_body<float, 2048, 0>(b, k, blk, smem); break;
-    case 12: sweep_body<float, 4096, 0>(b, k, blk, smem); break;
-    default: break;
-    }
-}
-
 // x-advection by dt = b.a[sim] directly on the v-fastest layout f[nx][nv]
 // (N = nx): a block owns the x-lines j0 .. j0 + B - 1, i.e. the tile
 // f[0..N)[j0..j0+B), and runs the packed line-pair transform on B / 2 pairs
@@ -635,197 +618,6 @@ __global__ __launch_bounds__((kFusedThreads<T, N>), (Fused<T, N>::WAVES)) void x
     __shared__ T smem[Fused<T, N>::SMEM];
     xsweep_body<T, N>(b, (int)blockIdx.y, (int)blockIdx.x, smem);
 }
-
-// FP32 x-sweeps of sims with x-lines of 64 .. 1024 points in one launch
-// (256-thread blocks for all of them).  Each sim's first block is a multiple
-// of 8, so the XCD-aware tile order holds.
-__global__ __launch_bounds__(256, 3) void xsweep_mixed_kernel(const Batch b, const BlockMap m) {
-    __shared__ float smem[Fused<float, 64>::SMEM];  // the largest of 64 .. 1024
-    const int bid = (int)blockIdx.x;
-    const int k = mixed_sim(b, m, bid);
-    const int hb = bid - m.first[k];
-    switch (m.lgn[k]) {
-    case 6: xsweep_body<float, 64>(b, k, hb, smem); break;
-    case 7: xsweep_body<float, 128>(b, k, hb, smem); break;
-    case 8: xsweep_body<float, 256>(b, k, hb, smem); break;
-    case 9: xsweep_body<float, 512>(b, k, hb, smem); break;
-    case 10: xsweep_body<float, 1024>(b, k, hb, smem); break;
-    default: break;
-    }
-}
-
-static_assert(Fused<float, 64>::TB == 256 && Fused<float, 1024>::TB == 256 &&
-                  Fused<float, 64>::WAVES == 3 && Fused<float, 1024>::WAVES == 3,
-              "mixed x-sweep: 256-thread blocks at 3 waves for 64 .. 1024 points");
-static_assert(Fused<float, 64>::SMEM >= Fused<float, 128>::SMEM &&
-                  Fused<float, 64>::SMEM >= Fused<float, 256>::SMEM &&
-                  Fused<float, 64>::SMEM >= Fused<float, 512>::SMEM &&
-                  Fused<float, 64>::SMEM >= Fused<float, 1024>::SMEM,
-              "mixed x-sweep LDS");
-static_assert(Sweep<float, 64>::SMEM >= Sweep<float, 128>::SMEM &&
-                  Sweep<float, 64>::SMEM >= Sweep<float, 256>::SMEM &&
-                  Sweep<float, 64>::SMEM >= Sweep<float, 512>::SMEM &&
-                  Sweep<float, 64>::SMEM >= Sweep<float, 1024>::SMEM &&
-                  Sweep<float, 64>::SMEM >= Sweep<float, 2048>::SMEM &&
-                  Sweep<float, 64>::SMEM >= Sweep<float, 4096>::SMEM,
-              "mixed v-sweep LDS");
-
-bool sweep_mixed_ok(bool vsweep, int n) {
-    const int logn = ilog2(n);
-    return (1 << logn) == n && n >= 64 && n <= (vsweep ? 4096 : 1024);
-}
-
-int sweep_blocks_mixed(bool vsweep, int n, int lines) {
-    if (!sweep_mixed_ok(vsweep, n)) return 0;
-    if (vsweep) {
-        const int ppb = 256 / (n / fft_regs(n));
-        return (lines / 2 + ppb - 1) / ppb;
-    }
-    const int tiles = lines / (2 * (256 / (n / fft_regs(n))));
-    return (tiles + 7) / 8 * 8;
-}
-
-void launch_sweep_mixed(bool vsweep, const Batch &b, const BlockMap &m, hipStream_t st) {
-    const int blocks = m.first[b.n];
-    if (vsweep) hipLaunchKernelGGL(sweep_v_mixed_kernel, dim3(blocks), dim3(256), 0, st, b, m);
-    else hipLaunchKernelGGL(xsweep_mixed_kernel, dim3(blocks), dim3(256), 0, st, b, m);
-}
-
-template <typename T, int N>
-static void launch_xsweep_fused(const Batch &b, int max_lines, hipStream_t st) {
-    using C = Fused<T, N>;
-    const int blocks = max_lines / C::B;
-    hipLaunchKernelGGL((xsweep_fused_kernel<T, N>), dim3(blocks, b.n), dim3(C::TB), 0, st, b);
-}
-
-template <typename T, int... L>
-static LaunchFn pick_fused(int logn, std::integer_sequence<int, L...>) {
-    LaunchFn fns[] = {&launch_xsweep_fused<T, (64 << L)>...};
-    return fns[logn - 6];
-}
-
-// Lines per tile of the x-sweep on the v-fastest layout for x-lines of nx
-// points (64 .. 4096), 0 where it does not apply.
-int fused_lines_per_block(bool fp64, int nx) {
-    const int logn = ilog2(nx);
-    if (nx < 64 || nx > VOG_MAX_N || (1 << logn) != nx) return 0;
-    constexpr int tf[7] = {Fused<float, 64>::B, Fused<float, 128>::B, Fused<float, 256>::B,
-                           Fused<float, 512>::B, Fused<float, 1024>::B, Fused<float, 2048>::B,
-                           Fused<float, 4096>::B};
-    constexpr int td[7] = {Fused<double, 64>::B, Fused<double, 128>::B, Fused<double, 256>::B,
-                           Fused<double, 512>::B, Fused<double, 1024>::B, Fused<double, 2048>::B,
-                           Fused<double, 4096>::B};
-    return fp64 ? td[logn - 6] : tf[logn - 6];
-}
-
-LaunchFn fused_xsweep_launcher(bool fp64, int nx) {
-    if (fused_lines_per_block(fp64, nx) == 0) return nullptr;
-    using Seq = std::make_integer_sequence<int, 7>;
-    return fp64 ? pick_fused<double>(ilog2(nx), Seq{}) : pick_fused<float>(ilog2(nx), Seq{});
-}
-
-template <typename T, int N, int KIND>
-static void launch_sweep(const Batch &b, int max_lines, hipStream_t st) {
-    constexpr int PPB = 256 / Fft<T, N>::TPF;
-    const int blocks = (max_lines / 2 + PPB - 1) / PPB;
-    hipLaunchKernelGGL((sweep_kernel<T, N, KIND>), dim3(blocks, b.n), dim3(256), 0, st, b);
-}
-
-template <typename T, int KIND, int... L>
-static LaunchFn pick_sweep(int logn, std::integer_sequence<int, L...>) {
-    LaunchFn fns[] = {&launch_sweep<T, (8 << L), KIND>...};
-    return fns[logn - 3];
-}
-
-LaunchFn sweep_launcher(bool fp64, int n, bool vsweep) {
-    const int logn = ilog2(n);
-    if (n < VOG_MIN_N || n > VOG_MAX_N || (1 << logn) != n) return nullptr;
-    using Seq = std::make_integer_sequence<int, 10>;
-    if (fp64) return vsweep ? pick_sweep<double, 0>(logn, Seq{}) : pick_sweep<double, 1>(logn, Seq{});
-    return vsweep ? pick_sweep<float, 0>(logn, Seq{}) : pick_sweep<float, 1>(logn, Seq{});
-}
-
-
-// ----------------------------------------------------------------- transpose
-
-// TO_V false: f [nx][nv] -> g [nv][nx].  TO_V true: g [nv][nx] -> f [nx][nv]
-// and part[jt][i] = FP64 sum of the tile's (up to 64) velocities of column
-// i, accumulated in a fixed order.  One 64 x 64 tile per block.
-template <typename T, bool TO_V>
-__global__ __launch_bounds__(256) void transpose_kernel(const Batch b) {
-    __shared__ T tile[kTile][kTile + 1];
-    const SimDev &S = *b.s[blockIdx.y];
-    const int rows = TO_V ? S.nv : S.nx;
-    const int cols = TO_V ? S.nx : S.nv;
-    const T *in = (const T *)(TO_V ? S.g : S.f);
-    T *out = (T *)(TO_V ? S.f : S.g);
-    const int tilesC = (cols + kTile - 1) / kTile;
-    const int tilesR = (rows + kTile - 1) / kTile;
-    const int tr = blockIdx.x / tilesC, tc = blockIdx.x % tilesC;
-    if (tr >= tilesR) return;
-    const int r0 = tr * kTile, c0 = tc * kTile;
-    const int tx = threadIdx.x & (kTile - 1), ty = threadIdx.x / kTile;
-    constexpr int kRows = 256 / kTile;  // tile rows handled per pass of the block
-#pragma unroll
-    for (int i = 0; i < kTile / kRows; ++i) {
-        const int rr = ty + i * kRows;
-        const int r = r0 + rr, c = c0 + tx;
-        if (r < rows && c < cols) tile[rr][tx] = in[(size_t)r * cols + c];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < kTile / kRows; ++i) {
-        const int cc = ty + i * kRows;
-        const int c = c0 + cc, r = r0 + tx;
-        if (r < rows && c < cols) out[(size_t)c * rows + r] = tile[tx][cc];
-    }
-    if constexpr (TO_V) {
-        if (threadIdx.x < kTile) {
-            const int c = c0 + threadIdx.x;
-            if (c < cols) {
-                const int nr = rows - r0 < kTile ? rows - r0 : kTile;
-                double acc = 0.0;
-                for (int rr = 0; rr < nr; ++rr) acc += (double)tile[rr][threadIdx.x];
-                S.part[(size_t)tr * cols + c] = acc;
-            }
-        }
-    }
-}
-
-// rho_i = dv sum_p part[p][i] + feq_const, partial rows summed in order.
-__global__ __launch_bounds__(256) void rho_reduce_kernel(const Batch b) {
-    __shared__ double red[4][kTile];
-    const SimDev &S = *b.s[blockIdx.y];
-    const int i = blockIdx.x * kTile + (threadIdx.x & (kTile - 1));
-    const int ty = threadIdx.x / kTile;
-    if ((int)blockIdx.x * kTile >= S.nx) return;
-    const int np = S.nparts;
-    double acc = 0.0;
-    if (i < S.nx)
-        for (int p = ty; p < np; p += 4) acc += S.part[(size_t)p * S.nx + i];
-    red[ty][threadIdx.x & (kTile - 1)] = acc;
-    __syncthreads();
-    if (ty == 0 && i < S.nx) {
-        const int tx = threadIdx.x;
-        S.rho[i] = S.dv * (((red[0][tx] + red[1][tx]) + red[2][tx]) + red[3][tx]) + S.feq_const;
-    }
-}
-
-void launch_rho_reduce(const Batch &b, int max_nx, hipStream_t st) {
-    hipLaunchKernelGGL(rho_reduce_kernel, dim3((max_nx + kTile - 1) / kTile, b.n), dim3(256), 0, st, b);
-}
-
-void launch_transpose(bool fp64, bool to_v, const Batch &b, int max_tiles, hipStream_t st) {
-    dim3 grid(max_tiles, b.n), block(256);
-    if (fp64) {
-        if (to_v) hipLaunchKernelGGL((transpose_kernel<double, true>), grid, block, 0, st, b);
-        else hipLaunchKernelGGL((transpose_kernel<double, false>), grid, block, 0, st, b);
-    } else {
-        if (to_v) hipLaunchKernelGGL((transpose_kernel<float, true>), grid, block, 0, st, b);
-        else hipLaunchKernelGGL((transpose_kernel<float, false>), grid, block, 0, st, b);
-    }
-}
-
 // ----------------------------------------------------------------- field solve
 
 // One block per sim, TPF = N/16 threads (N = nx).  rho_hat = FFT(rho) gives
@@ -1034,222 +826,4 @@ __global__ __launch_bounds__(kFieldThreads<N>) void field_kernel(const Batch b) 
     __shared__ double smem[Field<N>::SMEM];
     field_body<N>(b, (int)blockIdx.x, smem);
 }
-
-// Field solves of sims with 8 .. 1024 points in x, any mix of lengths, in
-// one launch: one wave per sim, whose first TPF lanes run the body of the
-// sim's length (a one-wave block needs no barrier between its lanes).
-__global__ __launch_bounds__(64) void field_mixed_kernel(const Batch b, const BlockMap m) {
-    __shared__ double smem[Field<1024>::SMEM];
-    const int k = (int)blockIdx.x;  // one block per sim
-    const int t = (int)threadIdx.x;
-    switch (m.lgn[k]) {
-    case 3: if (t < Field<8>::TPF) field_body<8>(b, k, smem); break;
-    case 4: if (t < Field<16>::TPF) field_body<16>(b, k, smem); break;
-    case 5: if (t < Field<32>::TPF) field_body<32>(b, k, smem); break;
-    case 6: if (t < Field<64>::TPF) field_body<64>(b, k, smem); break;
-    case 7: if (t < Field<128>::TPF) field_body<128>(b, k, smem); break;
-    case 8: if (t < Field<256>::TPF) field_body<256>(b, k, smem); break;
-    case 9: if (t < Field<512>::TPF) field_body<512>(b, k, smem); break;
-    case 10: field_body<1024>(b, k, smem); break;
-    default: break;
-    }
-}
-
-static_assert(Field<1024>::TPF == 64 && Field<1024>::SMEM >= Field<512>::SMEM,
-              "mixed field solve: one wave, LDS of the 1024-point body");
-
-bool field_mixed_ok(int nx) { return nx >= 8 && nx <= 1024 && (nx & (nx - 1)) == 0; }
-
-void launch_field_mixed(const Batch &b, const BlockMap &m, hipStream_t st) {
-    hipLaunchKernelGGL(field_mixed_kernel, dim3(b.n), dim3(64), 0, st, b, m);
-}
-
-template <int N>
-static void launch_field(const Batch &b, int, hipStream_t st) {
-    hipLaunchKernelGGL((field_kernel<N>), dim3(b.n), dim3(Fft<double, N>::TPF), 0, st, b);
-}
-
-// x-lines of 2048 and 4096 points (shorter ones go through field_mixed_kernel).
-LaunchFn field_launcher(int nx) {
-    if (nx == 2048) return &launch_field<2048>;
-    if (nx == 4096) return &launch_field<4096>;
-    return nullptr;
-}
-
-// ----------------------------------------------------------------- rho (v layout)
-
-// rho_i = dv sum_j f[i][j] + feq_const, FP64 accumulation in a fixed order:
-// one wave per x-column i (4 per block), 16-byte loads, xor-shuffle reduction.
-template <typename T>
-__global__ __launch_bounds__(256) void rho_v_kernel(const Batch b) {
-    const SimDev &S = *b.s[blockIdx.y];
-    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (i >= S.nx) return;  // wave-uniform; no block barrier follows
-    constexpr int VEC = 16 / sizeof(T);
-    const T *row = (const T *)S.f + (size_t)i * S.nv;
-    double acc = 0.0;
-    if (S.nv % (64 * VEC) == 0) {
-        for (int j = lane * VEC; j < S.nv; j += 64 * VEC) {
-            if constexpr (sizeof(T) == 4) {
-                const float4 x = *reinterpret_cast<const float4 *>(row + j);
-                acc += ((double)x.x + (double)x.y) + ((double)x.z + (double)x.w);
-            } else {
-                const double2 x = *reinterpret_cast<const double2 *>(row + j);
-                acc += x.x + x.y;
-            }
-        }
-    } else {
-        for (int j = lane; j < S.nv; j += 64) acc += (double)row[j];
-    }
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    if (lane == 0) S.rho[i] = S.dv * acc + S.feq_const;
-}
-
-void launch_rho_v(bool fp64, const Batch &b, int max_nx, hipStream_t st) {
-    const int blocks = (max_nx + 3) / 4;
-    if (fp64) hipLaunchKernelGGL((rho_v_kernel<double>), dim3(blocks, b.n), dim3(256), 0, st, b);
-    else hipLaunchKernelGGL((rho_v_kernel<float>), dim3(blocks, b.n), dim3(256), 0, st, b);
-}
-
-// ----------------------------------------------------------------- moments
-
-// mom[i] = (sum_j f_ij^2, sum_j f_ij v_j^2) of the full f (f_eq added back
-// for delta f), FP64, fixed order.
-template <typename T>
-__global__ __launch_bounds__(256) void moments_line_kernel(const Batch b) {
-    __shared__ double r1[256], r2[256];
-    const SimDev &S = *b.s[blockIdx.y];
-    const int i = blockIdx.x;
-    if (i >= S.nx) return;
-    const T *row = (const T *)S.f + (size_t)i * S.nv;
-    double a1 = 0.0, a2 = 0.0;
-    for (int j = threadIdx.x; j < S.nv; j += 256) {
-        double f = (double)row[j];
-        if (S.deltaf) f += S.feq64[j];
-        const double vj = S.vmin + j * S.dv;
-        a1 += f * f;
-        a2 += f * vj * vj;
-    }
-    r1[threadIdx.x] = a1;
-    r2[threadIdx.x] = a2;
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) {
-            r1[threadIdx.x] += r1[threadIdx.x + h];
-            r2[threadIdx.x] += r2[threadIdx.x + h];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        S.mom[2 * i] = r1[0];
-        S.mom[2 * i + 1] = r2[0];
-    }
-}
-
-// L2 = dx dv sum f^2; energy = dx dv sum f v^2 / 2 + dx / 2 sum E^2
-// (Section 4.2), written into the step's diagnostics record.
-__global__ __launch_bounds__(256) void moments_final_kernel(const Batch b) {
-    __shared__ double r1[256], r2[256], r3[256];
-    const SimDev &S = *b.s[blockIdx.x];
-    double a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    for (int i = threadIdx.x; i < S.nx; i += 256) {
-        a1 += S.mom[2 * i];
-        a2 += S.mom[2 * i + 1];
-        a3 += S.E[i] * S.E[i];
-    }
-    r1[threadIdx.x] = a1;
-    r2[threadIdx.x] = a2;
-    r3[threadIdx.x] = a3;
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) {
-            r1[threadIdx.x] += r1[threadIdx.x + h];
-            r2[threadIdx.x] += r2[threadIdx.x + h];
-            r3[threadIdx.x] += r3[threadIdx.x + h];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        vog_diag &d = S.ring[b.step[blockIdx.x] % kRingCap];
-        d.l2 = S.dx * S.dv * r1[0];
-        d.energy = 0.5 * S.dx * S.dv * r2[0] + 0.5 * S.dx * r3[0];
-    }
-}
-
-void launch_moments(bool fp64, const Batch &b, int max_nx, hipStream_t st) {
-    if (fp64) hipLaunchKernelGGL((moments_line_kernel<double>), dim3(max_nx, b.n), dim3(256), 0, st, b);
-    else hipLaunchKernelGGL((moments_line_kernel<float>), dim3(max_nx, b.n), dim3(256), 0, st, b);
-    hipLaunchKernelGGL(moments_final_kernel, dim3(b.n), dim3(256), 0, st, b);
-}
-
-// ----------------------------------------------------------------- init / fill
-
-struct InitArgs {
-    int nmodes;
-    double amp[8], kx[8], ph[8];
-};
-
-// f0 = (1 + sum_m amp_m cos(kx_m x_i + ph_m)) f_eq(v_j); delta f stores the
-// perturbation part only.
-template <typename T>
-__global__ __launch_bounds__(256) void init_kernel(const SimDev *sp, const InitArgs a) {
-    const SimDev &S = *sp;
-    const size_t cells = (size_t)S.nx * S.nv;
-    for (size_t idx = blockIdx.x * (size_t)256 + threadIdx.x; idx < cells;
-         idx += (size_t)gridDim.x * 256) {
-        const int i = (int)(idx / S.nv), j = (int)(idx % S.nv);
-        const double x = i * S.dx;
-        double p = 0.0;
-        for (int m = 0; m < a.nmodes; ++m) p += a.amp[m] * cos(a.kx[m] * x + a.ph[m]);
-        const double fe = S.feq64[j];
-        ((T *)S.f)[idx] = (T)(S.deltaf ? p * fe : (1.0 + p) * fe);
-    }
-}
-
-void launch_init(bool fp64, const SimDev *s, int cells, int nmodes, const double *amp,
-                 const double *kx, const double *ph, hipStream_t st) {
-    InitArgs a{};
-    a.nmodes = nmodes;
-    for (int m = 0; m < nmodes; ++m) {
-        a.amp[m] = amp[m];
-        a.kx[m] = kx[m];
-        a.ph[m] = ph[m];
-    }
-    int blocks = (cells + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
-    if (fp64) hipLaunchKernelGGL((init_kernel<double>), dim3(blocks), dim3(256), 0, st, s, a);
-    else hipLaunchKernelGGL((init_kernel<float>), dim3(blocks), dim3(256), 0, st, s, a);
-}
-
-__global__ __launch_bounds__(64) void finite_gather_kernel(const Batch b, int *out) {
-    const int k = (int)threadIdx.x;
-    if (k >= b.n) return;
-    const SimDev &S = *b.s[k];
-    const int64_t st = b.step[k];
-    int ok = 1;
-    if (st > 0 && !S.field_zero) {
-        const vog_diag &d = S.ring[st % kRingCap];
-        if (d.step == st && !d.finite) ok = 0;
-    }
-    out[k] = ok;
-}
-
-void launch_finite_gather(const Batch &b, int *out, hipStream_t st) {
-    hipLaunchKernelGGL(finite_gather_kernel, dim3(1), dim3(64), 0, st, b, out);
-}
-
-__global__ __launch_bounds__(256) void fill_kernel(uint32_t *p, size_t nwords) {
-    for (size_t k = blockIdx.x * (size_t)256 + threadIdx.x; k < nwords; k += (size_t)gridDim.x * 256)
-        p[k] = 0u;
-}
-
-void launch_fill(void *p, size_t bytes, hipStream_t st) {
-    const size_t nwords = bytes / 4;
-    if (nwords == 0) return;
-    size_t blocks = (nwords + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks), dim3(256), 0, st, (uint32_t *)p, nwords);
-}
-
 }  // namespace vog
