@@ -139,21 +139,29 @@ __device__ __forceinline__ P opaque(P p) {
     return p;
 }
 
-// Loads entries [0, n) of a table row (n even, row 16-byte aligned).
+// Loads entries [0, n) of a table row (n even, row 16-byte aligned).  The
+// tables live in global memory: the loads are global ones (a flat load would
+// also count as an LDS access).
 template <typename T, int NE>
 __device__ __forceinline__ void load_row(const cx<T> *__restrict__ row, cx<T> (&out)[NE]) {
     if constexpr (sizeof(T) == 4) {
-        const float4 *p = reinterpret_cast<const float4 *>(row);
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        typedef __attribute__((address_space(1))) const f4 gf4;
+        gf4 *p = (gf4 *)row;
         static_for<0, NE / 2>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
-            const float4 q = p[i];
+            const f4 q = p[i];
             out[2 * i] = cx<T>{q.x, q.y};
             out[2 * i + 1] = cx<T>{q.z, q.w};
         });
     } else {
+        typedef T d2 __attribute__((ext_vector_type(2)));
+        typedef __attribute__((address_space(1))) const d2 gd2;
+        gd2 *p = (gd2 *)row;
         static_for<0, NE>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
-            out[i] = row[i];
+            const d2 q = p[i];
+            out[i] = cx<T>{q.x, q.y};
         });
     }
 }

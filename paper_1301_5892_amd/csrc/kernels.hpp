@@ -144,6 +144,17 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void *base, uns
                                              kBufWord3);
 }
 
+// A value the same in every lane, moved to scalar registers.
+__device__ __forceinline__ double uniform_d(double x) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, x);
+    const uint64_t lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)u);
+    const uint64_t hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(u >> 32));
+    return __builtin_bit_cast(double, (hi << 32) | lo);
+}
+__device__ __forceinline__ long long uniform_ll(long long x) {
+    return (long long)__builtin_bit_cast(uint64_t, uniform_d(__builtin_bit_cast(double, x)));
+}
+
 template <typename T>
 __device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
     if constexpr (sizeof(T) == 4)
@@ -162,6 +173,11 @@ __device__ __forceinline__ void buf_store(T x, __amdgpu_buffer_rsrc_t r, unsigne
     }
 }
 
+}  // namespace vog
+
+#include "pair4096.hpp"  // uses fma_t, kTaps
+
+namespace vog {
 // ----------------------------------------------------------------- sweep
 
 // delta-f source of one line along the thread's output positions
@@ -202,18 +218,69 @@ __device__ __forceinline__ void deltaf_source(const SimDev &S, double tauE, int 
     }
 }
 
+// Stores a transformed line pair: out(k) (k a compile-time index) is the
+// result at unshifted position t + TPF k, lines A (real part) and B
+// (imaginary part).  Unshifted index j goes to line position (j - b) mod N;
+// pos[k] is the byte offset of position (p0 + k TPF) mod N in a line.
+// VSWEEP: adds the delta-f source (Section 3.1) with tau E of each line.
+template <typename T, int N, int R, int TPF, bool VSWEEP, typename Out>
+__device__ __forceinline__ void store_pair(const SimDev &S, double tauEA, double tauEB, long long bA,
+                                           long long bB, int t, __amdgpu_buffer_rsrc_t rA, unsigned oA,
+                                           __amdgpu_buffer_rsrc_t rB, unsigned oB, Out &&out) {
+    constexpr unsigned LB = N * sizeof(T);  // bytes per line
+    const int p0A = (t - (int)(bA & (N - 1))) & (N - 1);
+    const int p0B = (t - (int)(bB & (N - 1))) & (N - 1);
+    auto positions = [&](int p0, unsigned (&pos)[R]) {
+        const unsigned p = (unsigned)p0 * sizeof(T);
+        static_for<0, R>([&](auto kc) {
+            constexpr unsigned k = decltype(kc)::value;
+            pos[k] = (p + k * TPF * sizeof(T)) & (LB - 1);
+        });
+    };
+    unsigned pos[R];
+    if constexpr (VSWEEP) {
+        if (S.deltaf) {
+            T src[R];
+            positions(p0A, pos);
+            deltaf_source<T, N, R, TPF>(S, tauEA, p0A, pos, src);
+            static_for<0, R>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                buf_store<T>(out(kc).re + src[k], rA, oA + pos[k], 0);
+            });
+            positions(p0B, pos);
+            deltaf_source<T, N, R, TPF>(S, tauEB, p0B, pos, src);
+            static_for<0, R>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                buf_store<T>(out(kc).im + src[k], rB, oB + pos[k], 0);
+            });
+            return;
+        }
+    }
+    positions(p0A, pos);
+    static_for<0, R>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        buf_store<T>(out(kc).re, rA, oA + pos[k], 0);
+    });
+    positions(p0B, pos);
+    static_for<0, R>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        buf_store<T>(out(kc).im, rB, oB + pos[k], 0);
+    });
+}
+
 // Weights of a line pair for its fractional shifts sA, sB, combined for the
 // packed transform: wP = (wA + wB) / (2N), wQ = (wA - wB) / (2N) (the 1/N
-// folds the scale of the inverse FFT).  Threads t = 0.. of the pair share the
+// folds the scale of the inverse FFT), times `half` (0.5 for the 4096-point
+// transform, which builds its symbols from (wP + i wQ) / 2).  Threads t = 0.. of the pair share the
 // 2 x kTaps values; visible to the pair after the next barrier.
 template <typename T, int N, int TPF>
 __device__ __forceinline__ void pair_weights(int d, int interp, double sA, double sB, int t, T *wP,
-                                             T *wQ) {
+                                             T *wQ, double half = 1.0) {
     for (int qi = t; qi < kTaps; qi += TPF) {
         const int q = qi - kDMax;
         const double wa = interp ? bspline_weight(d, q, sA) : lagrange_weight(d, q, sA);
         const double wb = interp ? bspline_weight(d, q, sB) : lagrange_weight(d, q, sB);
-        const double sc = 0.5 / (double)N;
+        const double sc = 0.5 * half / (double)N;
         wP[qi] = (T)((wa + wb) * sc);
         wQ[qi] = (T)((wa - wb) * sc);
     }
@@ -409,7 +476,19 @@ __device__ __forceinline__ void sweep_body(const Batch &b, int sim, int blk, T *
     double sA, sB;
     split_shift(betaA, bA, sA);
     split_shift(betaB, bB, sB);
-    pair_weights<T, N, TPF>(S.d, S.interp, sA, sB, t, wsh[slot][0], wsh[slot][1]);
+    if constexpr (PPB == 1) {
+        // the same in every lane: keep them in scalar registers for the store
+        bA = uniform_ll(bA);
+        bB = uniform_ll(bB);
+        EA = uniform_d(EA);
+        EB = uniform_d(EB);
+    }
+    // FP64 4096-point lines: the four-wave digit transform of pair4096.hpp
+    // (measured faster there; for FP32 the radix-16 Stockham transform below
+    // is)
+    constexpr bool kP4k = N == 4096 && sizeof(T) == 8;
+    static_assert(!kP4k || (PPB == 1 && TPF == 256), "one 4096-point pair per 256-thread block");
+    pair_weights<T, N, TPF>(S.d, S.interp, sA, sB, t, wsh[slot][0], wsh[slot][1], kP4k ? 0.5 : 1.0);
 
     // Load the two lines packed as z = uA + i uB (a slot past the last pair
     // reads lines 0 and 1 and stores nothing).
@@ -423,54 +502,38 @@ __device__ __forceinline__ void sweep_body(const Batch &b, int sim, int blk, T *
         });
     }
 
+    // Y[i] holds the result at position t + TPF kpos(i) (kP4k: kpos(i) = i)
     cx<T> Y[R];
-    // a line pair of at most 1024 points is one wave's contiguous lanes
-    pair_transform<T, N, (sizeof(T) == 8), (TPF <= 64)>(
-        v, Y, t, lre, lim, tw, eps, wsh[slot][0], wsh[slot][1],
-        (const T *)(KIND == 0 ? S.iden_v : S.iden_x));
+    const T *iden = (const T *)(KIND == 0 ? S.iden_v : S.iden_x);
+    if constexpr (kP4k) {
+        const cx<T> *eps0 = (const cx<T> *)(KIND == 0 ? S.eps_v : S.eps_x);
+        {
+            cx<T> w[16];
+            p4k_col_row<T>(tw, t, w);
+            p4k_fwd_col<T>(v, t, lre, lim, w);
+        }
+        __syncthreads();
+        p4k_lanes<T>(t >> 6, t & 63, lre, lim, LoadRows<T>{tw, eps0}, wsh[0][0], iden);
+        __syncthreads();
+        {
+            cx<T> w[16];
+            p4k_col_row<T>(opaque(tw), t, w);  // re-read, not kept live
+            p4k_inv_col<T>(Y, t, lre, lim, w);
+        }
+    } else {
+        // a line pair of at most 1024 points is one wave's contiguous lanes
+        pair_transform<T, N, (sizeof(T) == 8), (TPF <= 64)>(v, Y, t, lre, lim, tw, eps, wsh[slot][0],
+                                                            wsh[slot][1], iden);
+    }
+    auto out = [&](auto kc) -> const cx<T> & {
+        constexpr int k = decltype(kc)::value;
+        if constexpr (kP4k) return Y[k];
+        else return Y[F::kinv(k)];
+    };
 
     if (!active) return;
 
-    // Store: unshifted index j goes to line position (j - b) mod N; pos[k] is
-    // the byte offset of position (p0 + k TPF) mod N in a line.
-    const int p0A = (t - (int)(bA & (N - 1))) & (N - 1);
-    const int p0B = (t - (int)(bB & (N - 1))) & (N - 1);
-    auto positions = [&](int p0, unsigned (&pos)[R]) {
-        const unsigned p = (unsigned)p0 * sizeof(T);
-        static_for<0, R>([&](auto kc) {
-            constexpr unsigned k = decltype(kc)::value;
-            pos[k] = (p + k * TPF * sizeof(T)) & (LB - 1);
-        });
-    };
-    unsigned pos[R];
-    if constexpr (KIND == 0) {
-        if (S.deltaf) {
-            T src[R];
-            positions(p0A, pos);
-            deltaf_source<T, N, R, TPF>(S, arg * EA, p0A, pos, src);
-            static_for<0, R>([&](auto kc) {
-                constexpr int k = decltype(kc)::value;
-                buf_store<T>(Y[F::kinv(k)].re + src[k], rA, oA + pos[k], 0);
-            });
-            positions(p0B, pos);
-            deltaf_source<T, N, R, TPF>(S, arg * EB, p0B, pos, src);
-            static_for<0, R>([&](auto kc) {
-                constexpr int k = decltype(kc)::value;
-                buf_store<T>(Y[F::kinv(k)].im + src[k], rB, oB + pos[k], 0);
-            });
-            return;
-        }
-    }
-    positions(p0A, pos);
-    static_for<0, R>([&](auto kc) {
-        constexpr int k = decltype(kc)::value;
-        buf_store<T>(Y[F::kinv(k)].re, rA, oA + pos[k], 0);
-    });
-    positions(p0B, pos);
-    static_for<0, R>([&](auto kc) {
-        constexpr int k = decltype(kc)::value;
-        buf_store<T>(Y[F::kinv(k)].im, rB, oB + pos[k], 0);
-    });
+    store_pair<T, N, R, TPF, KIND == 0>(S, arg * EA, arg * EB, bA, bB, t, rA, oA, rB, oB, out);
 }
 
 // One line length per launch: blockIdx.y = sim, blockIdx.x = block.
