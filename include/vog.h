@@ -230,6 +230,18 @@ int vog_sync(vog_sim *sim);
  * share the device and stream. */
 int vog_sync_batch(vog_sim *const *sims, int nsims, int *status);
 
+/* vog_sync_batch without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, results and errors as vog_sync_batch;
+ * the flags are gathered into a fixed array of VOG_NOALLOC_MAX_SIMS ints in
+ * the library's own device memory (one per GPU, held until the process
+ * ends), every flag written before it is read.  nsims above
+ * VOG_NOALLOC_MAX_SIMS is rejected with VOG_EINVAL.  Calls that overlap on
+ * one GPU share that array and race; the library serialises calls made
+ * through it, other users of the array must not overlap with them. */
+#define VOG_NOALLOC_MAX_SIMS 1024
+int vog_sync_batch_noalloc(vog_sim *const *sims, int nsims, int *status);
+
 void vog_destroy(vog_sim *sim);
 
 const char *vog_strerror(int code);

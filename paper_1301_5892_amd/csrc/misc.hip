@@ -2,6 +2,8 @@
 // the dispatch of the single-length sweep launchers.
 #include "kernels.hpp"
 
+#include <mutex>
+
 namespace vog {
 
 LaunchFn sweep_launcher_f32(int n, bool vsweep);
@@ -254,6 +256,25 @@ __global__ __launch_bounds__(64) void finite_gather_kernel(const Batch b, int *o
 
 void launch_finite_gather(const Batch &b, int *out, hipStream_t st) {
     hipLaunchKernelGGL(finite_gather_kernel, dim3(1), dim3(64), 0, st, b, out);
+}
+
+// Flag buffer of vog_sync_batch_noalloc: a fixed array in the library's own
+// device memory (one copy per GPU, held until the process ends) in place of
+// an allocation.  Host code never passes the array's name to a kernel: it
+// passes the address hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) int scratch[kNoAllocFlags];
+
+int *noalloc_flags(int device) {
+    static std::mutex mu;
+    static int *addr[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> g(mu);
+    if (!addr[device]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+        addr[device] = (int *)p;
+    }
+    return addr[device];
 }
 
 __global__ __launch_bounds__(256) void fill_kernel(uint32_t *p, size_t nwords) {

@@ -1167,6 +1167,41 @@ int vog_sync_batch(vog_sim *const *sims, int nsims, int *status) {
     return VOG_OK;
 }
 
+int vog_sync_batch_noalloc(vog_sim *const *sims, int nsims, int *status) {
+    if (!sims || nsims < 1 || !status) return fail(VOG_EINVAL, "NULL argument or nsims < 1");
+    if (nsims > VOG_NOALLOC_MAX_SIMS) return fail(VOG_EINVAL, "nsims exceeds VOG_NOALLOC_MAX_SIMS");
+    for (int k = 0; k < nsims; ++k) {
+        if (!sims[k]) return fail(VOG_EINVAL, "sim is NULL");
+        if (sims[k]->device != sims[0]->device || sims[k]->stream != sims[0]->stream)
+            return fail(VOG_EINVAL, "sims of a batch must share the device and stream");
+    }
+    vog_sim *lead = sims[0];
+    int rc = device_guard(lead);
+    if (rc != VOG_OK) return rc;
+    static std::mutex mu;  // calls through this entry point share the array
+    std::lock_guard<std::mutex> g(mu);
+    int *flags = noalloc_flags(lead->device);
+    if (!flags) return fail(VOG_EDEVICE, "address of the library's flag array not found");
+    // every flag 0 .. nsims-1 is written by the gathers before the copy reads it
+    for (int base = 0; base < nsims; base += kMaxBatch) {
+        Batch b{};
+        b.n = std::min(kMaxBatch, nsims - base);
+        for (int k = 0; k < b.n; ++k) {
+            b.s[k] = sims[base + k]->dev;
+            b.step[k] = sims[base + k]->step;
+        }
+        launch_finite_gather(b, flags + base, lead->stream);
+        if ((rc = check_launch()) != VOG_OK) return rc;
+    }
+    HIP_TRY(hipMemcpyAsync(status, flags, sizeof(int) * (size_t)nsims, hipMemcpyDeviceToHost, lead->stream));
+    HIP_TRY(hipStreamSynchronize(lead->stream));
+    for (int k = 0; k < nsims; ++k) {
+        sims[k]->staging.clear();
+        status[k] = status[k] ? VOG_OK : VOG_ENONFINITE;
+    }
+    return VOG_OK;
+}
+
 void vog_destroy(vog_sim *s) {
     if (!s) return;
     (void)hipStreamSynchronize(s->stream);

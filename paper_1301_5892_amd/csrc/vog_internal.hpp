@@ -93,5 +93,10 @@ void launch_fill(void *p, size_t bytes, hipStream_t st);
 // out[k] = 0 if sim k's diagnostics record of step b.step[k] says its field
 // is not finite, else 1 (k < b.n).
 void launch_finite_gather(const Batch &b, int *out, hipStream_t st);
+// Device address of the library's fixed flag array (kNoAllocFlags ints) on
+// `device`, which must be the current device; null if it cannot be found.
+constexpr int kNoAllocFlags = VOG_NOALLOC_MAX_SIMS;
+constexpr int kMaxDevices = 64;
+int *noalloc_flags(int device);
 
 }  // namespace vog

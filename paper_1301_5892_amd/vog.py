@@ -17,6 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libvog.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, EBUSY = 0, -1, -2, -3, -4, -5
+NOALLOC_MAX_SIMS = 1024  # VOG_NOALLOC_MAX_SIMS of vog.h
 FP64_PLAIN, FP32_DELTAF, FP64_DELTAF, FP32_PLAIN = 0, 1, 2, 3
 INTERP_LAGRANGE, INTERP_BSPLINE = 0, 1
 POISSON_FOURIER, POISSON_TRAPEZOID = 0, 1
@@ -70,7 +71,7 @@ EXPORTS = ["vog_config_default", "vog_config_validate", "vog_workspace_bytes", "
            "vog_init_perturbed", "vog_set_f", "vog_get_f", "vog_get_raw", "vog_get_E",
            "vog_set_E", "vog_step", "vog_step_batch", "vog_sweep", "vog_get_diag",
            "vog_state_bytes", "vog_get_state", "vog_set_state", "vog_get_time", "vog_sync", "vog_sync_batch",
-           "vog_destroy", "vog_strerror", "vog_last_error", "vog_profile_enable",
+           "vog_sync_batch_noalloc", "vog_destroy", "vog_strerror", "vog_last_error", "vog_profile_enable",
            "vog_profile_read", "vog_build_info"]
 
 _lib = None
@@ -111,6 +112,7 @@ def load() -> ctypes.CDLL:
                                         ctypes.POINTER(ctypes.c_double)]),
         "vog_sync": (ctypes.c_int, [_P]),
         "vog_sync_batch": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
+        "vog_sync_batch_noalloc": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
         "vog_destroy": (None, [_P]),
         "vog_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "vog_last_error": (ctypes.c_char_p, []),

@@ -129,3 +129,14 @@ def test_serving_mix_is_seeded():
         assert 200 <= r.workload.nsteps <= 2000
         assert 1e-3 <= r.workload.amp[0] <= 0.5
         assert abs(r.workload.L * r.workload.kx[0] - 2 * math.pi) < 1e-12
+
+
+def test_noalloc_sync_batch_rejects_bad_arguments_on_the_host(vog):
+    # argument checks come before any device work
+    L = vog.load()
+    st = (ctypes.c_int * 2)()
+    assert L.vog_sync_batch_noalloc(None, 1, st) == vog.EINVAL
+    assert L.vog_sync_batch_noalloc((vog._P * 1)(None), 1, st) == vog.EINVAL
+    assert L.vog_sync_batch_noalloc((vog._P * 1)(None), 0, st) == vog.EINVAL
+    n = vog.NOALLOC_MAX_SIMS + 1
+    assert L.vog_sync_batch_noalloc((vog._P * n)(), n, (ctypes.c_int * n)()) == vog.EINVAL
