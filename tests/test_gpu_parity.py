@@ -7,6 +7,7 @@ Both sides start from the same seeded inputs (workloads); the oracle computes
 every expected value itself.
 """
 import math
+import sys
 
 import numpy as np
 import pytest
@@ -18,6 +19,11 @@ pytestmark = pytest.mark.gpu
 
 TOL64 = 1e-12
 TOL32 = 1e-5
+# FP64 E and ||E||_2 after several steps: E comes from rho - mean(rho), and the
+# rounding of the nv-term sums that give rho (about eps sqrt(nv) max rho, in any
+# implementation) is amplified by max rho / max|rho - mean rho| (up to about 1e3
+# on these workloads): about 2e-12 on the large grid, so the gate is 1e-11.
+TOL64_E = 1e-11
 
 
 def rel(a, b):
@@ -27,8 +33,10 @@ def rel(a, b):
 
 def rel_field(E, o):
     """E error relative to (L / 2 pi) max|rho|, the field a unit relative
-    error of rho produces: E comes from rho - mean(rho), so when |E| is far
-    below that scale the rounding of rho dominates its relative error."""
+    error of rho produces.  Only for driven runs that start from f = f_M
+    (KEEN waves), where the self-consistent E starts at rounding level and
+    grows from the drive: its error then follows the rounding of rho, not
+    the size of E.  Every other run compares E relative to max|E|."""
     scale = max(np.max(np.abs(o.E)), o.w.L / (2 * math.pi) * np.max(np.abs(o.rho)))
     return float(np.max(np.abs(np.asarray(E) - o.E)) / scale)
 
@@ -192,11 +200,11 @@ def test_landau_weak_fp64_full_run(gpu):
     s.step(w.nsteps)
     od = o.step(w.nsteps)
     assert rel(s.get_f(), o.f) < TOL64
-    assert rel(s.get_E(), o.E) < 1e-11
+    assert rel(s.get_E(), o.E) < TOL64_E
     d = s.diag()
     assert d.size == w.nsteps + 1
     assert np.all(d["finite"] == 1)
-    assert np.max(np.abs(d["normE"][1:] - od[:, 0]) / od[:, 0]) < 1e-10
+    assert np.max(np.abs(d["normE"][1:] - od[:, 0]) / od[:, 0]) < TOL64_E
     t = d["t"][1:]
     gamma, omega, _ = oracle.landau_fit(t, d["normE"][1:])
     assert abs(-gamma - 0.1533) / 0.1533 < 0.05
@@ -255,7 +263,7 @@ def test_landau_fp64_deltaf_matches_oracle(gpu):
     s.step(30)
     o.step(30)
     assert rel(s.get_raw(), o.f) < TOL64
-    assert rel(s.get_E(), o.E) < 1e-11
+    assert rel(s.get_E(), o.E) < TOL64_E
 
 
 @pytest.mark.parametrize("nsteps", [1, 10])
@@ -277,6 +285,7 @@ def test_landau_strong_fp64_plain(gpu, nsteps):
     s.step(nsteps)
     o.step(nsteps)
     assert rel(s.get_f(), o.f) < TOL64
+    assert rel(s.get_E(), o.E) < TOL64_E
 
 
 @pytest.mark.parametrize("nsteps", [1, 10])
@@ -290,16 +299,20 @@ def test_bump_on_tail_fp32_deltaf(gpu, nsteps):
     assert rel(s.get_E(), o.E) < TOL32
 
 
-@pytest.mark.parametrize("precision,tol", [("fp32_deltaf", TOL32), ("fp64_plain", TOL64)])
-def test_large_grid_full_size(gpu, precision, tol):
+@pytest.mark.parametrize("nsteps", [1, 10])
+@pytest.mark.parametrize("precision,tol,tolE", [("fp32_deltaf", TOL32, TOL32),
+                                                ("fp64_plain", TOL64, TOL64_E)])
+def test_large_grid_full_size(gpu, precision, tol, tolE, nsteps):
+    # the 4096 x 4096 grid at full size, in the launch configuration the
+    # benchmark times, after 1 and 10 steps
     w = workloads.large_grid().replace(precision=precision)
     s = sim_of(gpu, w).init()
     o = oracle.Oracle(w).init()
-    s.step(2)
-    o.step(2)
+    s.step(nsteps)
+    o.step(nsteps)
     got = s.get_raw() if precision == "fp32_deltaf" else s.get_f()
     assert rel(got, o.f) < tol
-    assert rel(s.get_E(), o.E) < max(tol, 1e-11)
+    assert rel(s.get_E(), o.E) < tolE
 
 
 # ---------------------------------------------------------------- runtime behaviour
@@ -393,7 +406,7 @@ def test_trapezoid_steps(gpu, precision, tol):
     o.step(10)
     got = s.get_raw() if precision == "fp32_deltaf" else s.get_f()
     assert rel(got, o.f) < tol
-    assert rel(s.get_E(), o.E) < max(tol, 1e-11)
+    assert rel(s.get_E(), o.E) < (TOL64_E if precision == "fp64_plain" else tol)
 
 
 @pytest.mark.parametrize("n,precision,tol,nsteps", [(64, "fp64_plain", TOL64, 30),
@@ -415,10 +428,11 @@ def test_keen_driven(gpu, n, precision, tol, nsteps):
     else:
         assert rel_field(s.get_E(), o) < tol
     dg = s.diag()
-    assert np.max(np.abs(dg["normE"][1:] - od[:, 0]) / od[:, 0]) < max(tol, 1e-9)
+    tolE = TOL64_E if precision == "fp64_plain" else tol
+    assert np.max(np.abs(dg["normE"][1:] - od[:, 0]) / od[:, 0]) < tolE
     modes = o.rho_modes(7)
-    # |rho_hat_m|, m = 1..7, compared at the parity tolerance relative to the largest mode
-    assert np.max(np.abs(dg["abs_rho_modes"][-1] - modes)) < max(tol, 1e-9) * np.max(modes)
+    # |rho_hat_m|, m = 1..7, compared relative to the largest mode
+    assert np.max(np.abs(dg["abs_rho_modes"][-1] - modes)) < tolE * np.max(modes)
 
 
 def test_drive_checkpoint_bitwise(gpu):
@@ -434,3 +448,56 @@ def test_drive_checkpoint_bitwise(gpu):
     c.set_state(b.get_state())
     c.step(5)
     assert np.array_equal(c.get_raw(), ref)
+
+
+# ---------------------------------------------------------------- long horizons
+
+def _fp32_rounded(o):
+    """A second oracle state whose stored f0 is o's rounded to FP32."""
+    r = oracle.Oracle(o.w).init()
+    r.f = np.ascontiguousarray(o.f.astype(np.float32).astype(np.float64))
+    r.update_field()
+    return r
+
+
+def _fp32_error_curve(gpu, w, gates, mass_drift):
+    """The FP32 delta-f run against the FP64 oracle over a long horizon.
+
+    Nonlinear runs amplify round-off.  Rounding f0 to FP32 alone keeps an
+    FP64 run within 1e-5 of the exact one far longer than these horizons
+    (measured beside: the oracle from f0 rounded to FP32); what limits the
+    FP32 path is the rounding of every sweep (FP32 FFTs of the line length),
+    which grows the error about linearly at first: 1e-5 is reached after
+    about 30 steps.  gates: (step, bound) on the relative max-norm error of
+    delta f and of E, 1e-5 where the parity gate holds and the measured curve
+    with a margin of three or more beyond it.  mass_drift: bound on
+    |rho_hat_0(n) - rho_hat_0(0)| of the GPU run over the horizon."""
+    o = oracle.Oracle(w).init()
+    r = _fp32_rounded(o)
+    s = sim_of(gpu, w).init()
+    done = 0
+    for n, bound in gates:
+        o.step(n - done)
+        r.step(n - done)
+        s.step(n - done)
+        done = n
+        err, errE = rel(s.get_raw(), o.f), rel(s.get_E(), o.E)
+        assert rel(r.f, o.f) < TOL32      # the rounded start alone stays inside 1e-5
+        sys.__stderr__.write(f"\n{w.name} step {n}: FP32 error {err:.2e} (E {errE:.2e}), "
+                             f"oracle from FP32 f0 {rel(r.f, o.f):.2e}\n")
+        assert err < bound and errE < bound, (w.name, n, err, errE, bound)
+    d = s.diag()
+    assert np.all(d["finite"] == 1)
+    assert np.max(np.abs(d["rho0"] - d["rho0"][0])) < mass_drift
+
+
+def test_strong_landau_long_run(gpu):
+    # measured (MI355X): 1.1e-5 at step 40, 3.2e-5 at 100, 2.6e-4 at 300
+    _fp32_error_curve(gpu, workloads.landau_strong(), [(20, TOL32), (100, 1e-4), (300, 1e-3)],
+                      mass_drift=1e-6)
+
+
+def test_bump_on_tail_long_run(gpu):
+    # measured (MI355X): 6.9e-6 at step 25, 2.8e-5 at 100, 1.8e-4 at 300
+    _fp32_error_curve(gpu, workloads.bump_on_tail(), [(25, TOL32), (100, 1e-4), (300, 1e-3)],
+                      mass_drift=1e-6)

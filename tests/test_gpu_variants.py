@@ -19,6 +19,7 @@ pytestmark = pytest.mark.gpu
 
 TOL64 = 1e-12
 TOL32 = 1e-5
+TOL64_E = 1e-11  # FP64 E and ||E||_2 after several steps (see test_gpu_parity.TOL64_E)
 
 
 def rel(a, b):
@@ -27,6 +28,9 @@ def rel(a, b):
 
 
 def rel_field(E, o):
+    """E error relative to (L / 2 pi) max|rho|: only for driven runs from
+    f = f_M, whose self-consistent E starts at rounding level (see
+    test_gpu_parity.rel_field)."""
     scale = max(np.max(np.abs(o.E)), o.w.L / (2 * math.pi) * np.max(np.abs(o.rho)))
     return float(np.max(np.abs(np.asarray(E) - o.E)) / scale)
 
@@ -117,9 +121,9 @@ def test_bspline_landau_run_fp64(gpu):
     s.step(30)
     od = o.step(30)
     assert rel(s.get_f(), o.f) < TOL64
-    assert rel_field(s.get_E(), o) < TOL64
+    assert rel(s.get_E(), o.E) < TOL64_E
     d = s.diag()
-    assert np.max(np.abs(d["normE"][1:] - od[:, 0]) / od[:, 0]) < 1e-9
+    assert np.max(np.abs(d["normE"][1:] - od[:, 0]) / od[:, 0]) < TOL64_E
 
 
 @pytest.mark.parametrize("k", [3, 5])
@@ -157,9 +161,9 @@ def test_merged_landau_fp64(gpu):
     s.step(w.nsteps)
     od = o.step(w.nsteps)
     assert rel(s.get_f(), o.f) < TOL64
-    assert rel_field(s.get_E(), o) < TOL64
+    assert rel(s.get_E(), o.E) < TOL64_E
     d = s.diag()
-    assert np.max(np.abs(d["normE"][1:] - od[:, 0]) / od[:, 0]) < 1e-9
+    assert np.max(np.abs(d["normE"][1:] - od[:, 0]) / od[:, 0]) < TOL64_E
 
 
 def test_merged_strong_fp32(gpu):
@@ -252,7 +256,7 @@ def test_fp32_plain_runs(gpu, poisson, zero_mean):
     s.step(10)
     o.step(10)
     assert rel(s.get_raw(), o.f) < TOL32
-    assert rel_field(s.get_E(), o) < TOL32
+    assert rel(s.get_E(), o.E) < TOL32
 
 
 # ---------------------------------------------------------------- precision study (Section 4.1)
@@ -389,7 +393,9 @@ def _mixed_fp32():
             base.replace(nx=128, nv=2048, precision="fp32_deltaf"),
             base.replace(nx=256, nv=256, precision="fp32_deltaf"),
             base.replace(nx=512, nv=512, precision="fp32_deltaf"),
-            base.replace(nx=64, nv=128, precision="fp32_plain"),
+            # (FP32 without delta f at a strong amplitude: rho - mean(rho) well
+            # above the rounding of f stored in FP32)
+            base.replace(nx=64, nv=128, precision="fp32_plain", amp=(0.5,)),
             spline(base.replace(nx=128, nv=1024, precision="fp32_deltaf"), 5),
             base.replace(nx=32, nv=64, precision="fp32_deltaf"),
             # v-lines of 32 points: their own launch beside the mixed one
@@ -417,13 +423,11 @@ def test_mixed_lengths_batch_matches_oracle(gpu):
     sims = [gpu.Sim(w).init() for w in ws]
     vog.step_batch(sims, 3)
     for w, s in zip(ws, sims):
-        if w.nx * w.nv > 128 * 1024:
-            continue
         o = oracle.Oracle(w).init()
         o.step(3)
         # stored arrays: delta f for the delta-f variants, f for plain FP32
         assert rel(s.get_raw(), o.f) < TOL32, w.name
-        assert rel_field(s.get_E(), o) < TOL32, w.name
+        assert rel(s.get_E(), o.E) < TOL32, w.name
 
 
 def test_mixed_lengths_more_sims_than_one_launch(gpu):
