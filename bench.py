@@ -50,7 +50,9 @@ def parse():
     p.add_argument("--no-merged", action="store_true",
                    help="skip the merged-v-half-step FP32 leg")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--cpu-seconds", type=float, default=12.0,
+                   help="oracle time on the headline workload (all threads); the one-thread "
+                        "and other-workload samples take about 0.8 of that again")
     p.add_argument("--no-serving", action="store_true")
     p.add_argument("--serving-requests", type=int, default=512)
     p.add_argument("--copy-calibration", action="store_true",
@@ -202,7 +204,20 @@ def roofline_for(w, precision, prof, steps):
     return hbm
 
 
-def cpu_baseline(w, seconds):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(w, seconds, max_steps=1000):
+    """Cell-updates/s of the FP64 oracle on w (delta-f form for delta-f
+    precisions): whole Strang steps from f0 until `seconds` have passed."""
     import oracle
     o = oracle.Oracle(w, deltaf=w.precision.endswith("deltaf")).init()
     steps = 0
@@ -211,12 +226,37 @@ def cpu_baseline(w, seconds):
         o.step(1)
         steps += 1
         el = time.perf_counter() - t0
-        if el >= seconds or steps >= 1000:
+        if el >= seconds or steps >= max_steps:
             break
-    return {"value": w.cells * steps / el, "unit": "cell-updates/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"{w.name}, {'delta-f' if o.deltaf else 'plain'} FP64 direct-stencil oracle, "
-                      f"{steps} Strang steps from f0 ({el:.1f} s)"}
+    return w.cells * steps / el, steps, el, o.deltaf
+
+
+def cpu_baseline(w, seconds):
+    """The oracle (plain C, FP64, OpenMP over lines) timed on the host: the
+    headline workload on all threads for about `seconds`, the same on one
+    thread, and the strong-Landau and bump-on-tail workloads truncated to a
+    few seconds each (per-step cost is constant, so a truncated run gives the
+    rate)."""
+    import oracle
+    import workloads
+    threads = oracle.num_threads()
+    rate, steps, el, df = _oracle_rate(w, seconds)
+    out = {"value": rate, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+           "cpu_model": cpu_model(),
+           "sample": f"{w.name}, {'delta-f' if df else 'plain'} FP64 direct-stencil oracle, "
+                     f"{steps} Strang steps from f0 ({el:.1f} s, {threads} threads)"}
+    oracle.set_num_threads(1)
+    try:
+        r1, s1, e1, _ = _oracle_rate(w, seconds / 3)
+    finally:
+        oracle.set_num_threads(threads)
+    out["one_thread"] = {"value": r1, "sample": f"{w.name}, {s1} steps ({e1:.1f} s, 1 thread)"}
+    other = {}
+    for wo in (workloads.landau_strong(), workloads.bump_on_tail()):
+        ro, so, eo, _ = _oracle_rate(wo, seconds / 5)
+        other[wo.name] = {"value": ro, "sample": f"{so} of {wo.nsteps} steps ({eo:.1f} s, {threads} threads)"}
+    out["other_workloads"] = other
+    return out
 
 
 # ---------------------------------------------------------------- rocprofv3 summaries

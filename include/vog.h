@@ -154,20 +154,29 @@ int vog_create(const vog_config *cfg, void *dev_workspace, size_t bytes,
 int vog_init_perturbed(vog_sim *sim, int nmodes, const double *amp, const double *kx,
                        const double *phase);
 
-/* Copies a full FP64 f (layout above) to the device; delta-f precisions store
- * f - f_eq rounded to the storage precision.  Recomputes E from f and resets
- * step counter, time and diagnostics. */
+/* Copies a full FP64 f (layout above: the distribution on the periodic
+ * Nx x Nv phase-space grid of the Introduction and Section 1.2) to the
+ * device; delta-f precisions store f - f_eq rounded to the storage precision
+ * (Section 3.1).  Recomputes E from f (Section 2: density, then field) and
+ * resets step counter, time and diagnostics.  host_f: nx*nv FP64 values,
+ * owned by the caller and not retained.  VOG_EINVAL for a NULL argument. */
 int vog_set_f(vog_sim *sim, const double *host_f);
 
-/* Copies the current full f to host FP64 (f_eq added back for delta f). */
+/* Copies the current full f (the phase-space grid of Section 1.2, layout
+ * above) to host FP64, f_eq added back for delta f (Section 3.1).  host_f:
+ * nx*nv FP64 values, owned by the caller.  Synchronises the sim's stream.
+ * VOG_EINVAL for a NULL argument. */
 int vog_get_f(vog_sim *sim, double *host_f);
 
 /* Copies the stored array (f or delta f, storage precision, same layout) to
  * host; elem_bytes receives 4 or 8.  host_buf holds nx*nv*elem_bytes bytes. */
 int vog_get_raw(vog_sim *sim, void *host_buf, size_t bytes, int *elem_bytes);
 
-/* Copies the self-consistent E at the current time level (nx FP64 values)
- * to host. */
+/* Copies the self-consistent E at the current time level (nx FP64 values at
+ * the nodes x_i = i dx; the field of the Poisson equation of Section 3.2 that
+ * the time loop of Section 2 updates every step) to host.  host_E: owned by
+ * the caller.  Synchronises the sim's stream.  VOG_EINVAL for a NULL
+ * argument. */
 int vog_get_E(vog_sim *sim, double *host_E);
 
 /* Replaces E (nx FP64 values) without touching f; the advecting field becomes
@@ -186,7 +195,8 @@ int vog_set_E(vog_sim *sim, const double *host_E);
  * returns after enqueueing.  dt > 0 and finite, nsteps >= 0 (0: no-op). */
 int vog_step(vog_sim *sim, double dt, int nsteps);
 
-/* nsteps Strang steps for nsims sims at once, sim k with step dt[k], with
+/* nsteps Strang steps (Section 1.1, the time loop of Section 2) for nsims
+ * sims at once, sim k with step dt[k], with
  * grouped launches of up to 64 sims: one per kernel type and line length, and
  * for FP32 sims one per sweep covering all their line lengths (v-lines of
  * 64..4096 points, x-lines of 64..1024).  Every sim must use the stream of

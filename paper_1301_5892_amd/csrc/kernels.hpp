@@ -27,6 +27,7 @@
 //  rho_v_kernel     rho = int f dv from the v-fastest layout; moments
 //                   kernels, init and fill helpers.
 
+#include "addr.hpp"
 #include "fft.hpp"
 #include "vog_internal.hpp"
 
@@ -135,11 +136,9 @@ constexpr int kBufWord3 = 0x00020000;
 // from the first active lane, so that the descriptor lives in scalar
 // registers and the compiler emits no per-lane loop around the accesses).
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void *base, unsigned bytes) {
-    // (readfirstlane works on int: widen through unsigned, never sign-extend)
     const uint64_t a = (uint64_t)base;
-    const uint64_t hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(a >> 32));
-    const uint64_t lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)a);
-    const uint64_t u = (hi << 32) | lo;
+    const uint64_t u = addr_join(__builtin_amdgcn_readfirstlane(addr_lo(a)),
+                                 __builtin_amdgcn_readfirstlane(addr_hi(a)));
     return __builtin_amdgcn_make_buffer_rsrc((void *)u, 0, (int)__builtin_amdgcn_readfirstlane(bytes),
                                              kBufWord3);
 }
@@ -147,9 +146,8 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void *base, uns
 // A value the same in every lane, moved to scalar registers.
 __device__ __forceinline__ double uniform_d(double x) {
     const uint64_t u = __builtin_bit_cast(uint64_t, x);
-    const uint64_t lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)u);
-    const uint64_t hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(u >> 32));
-    return __builtin_bit_cast(double, (hi << 32) | lo);
+    return __builtin_bit_cast(double, addr_join(__builtin_amdgcn_readfirstlane(addr_lo(u)),
+                                                __builtin_amdgcn_readfirstlane(addr_hi(u))));
 }
 __device__ __forceinline__ long long uniform_ll(long long x) {
     return (long long)__builtin_bit_cast(uint64_t, uniform_d(__builtin_bit_cast(double, x)));

@@ -34,6 +34,7 @@
 //   tw + 16 k,        k < 16:  exp(+2 pi i r k / 256),  r = 0..15
 //   tw + 256 + 16 k,  k < 256: exp(+2 pi i r k / 4096), r = 0..15.
 
+#include "addr.hpp"
 #include "fft.hpp"
 
 namespace vog {
@@ -67,9 +68,8 @@ __device__ __forceinline__ T uniform_t(T x) {
         return __builtin_bit_cast(T, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, x)));
     } else {
         const uint64_t u = __builtin_bit_cast(uint64_t, x);
-        const uint64_t lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)u);
-        const uint64_t hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(u >> 32));
-        return __builtin_bit_cast(T, (hi << 32) | lo);
+        return __builtin_bit_cast(T, addr_join(__builtin_amdgcn_readfirstlane(addr_lo(u)),
+                                               __builtin_amdgcn_readfirstlane(addr_hi(u))));
     }
 }
 
@@ -80,9 +80,8 @@ __device__ __forceinline__ T bperm(int addr, T x) {
         return __builtin_bit_cast(T, __builtin_amdgcn_ds_bpermute(addr, __builtin_bit_cast(int, x)));
     } else {
         const uint64_t u = __builtin_bit_cast(uint64_t, x);
-        const int lo = __builtin_amdgcn_ds_bpermute(addr, (int)(unsigned)u);
-        const int hi = __builtin_amdgcn_ds_bpermute(addr, (int)(unsigned)(u >> 32));
-        return __builtin_bit_cast(T, ((uint64_t)(unsigned)hi << 32) | (uint64_t)(unsigned)lo);
+        return __builtin_bit_cast(T, addr_join(__builtin_amdgcn_ds_bpermute(addr, addr_lo(u)),
+                                               __builtin_amdgcn_ds_bpermute(addr, addr_hi(u))));
     }
 }
 

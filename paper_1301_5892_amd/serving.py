@@ -283,10 +283,16 @@ def summarize(outcomes: Sequence[Outcome]) -> Dict[str, Any]:
     }
 
 
-def bench(n_requests: int = 512, load_factor: float = 0.8, quantum: int = 25,
-          max_active: int = 128, budget_bytes: int = 64 << 30, seed: int = 1) -> Dict[str, Any]:
-    """Serving mix: closed-loop capacity pass (all requests present at t=0),
-    then an open-loop pass with Poisson arrivals at load_factor x capacity."""
+def bench(n_requests: int = 512, load_factors: Sequence[float] = (0.5, 0.8, 1.0, 1.2),
+          headline_load: float = 0.8, quantum: int = 25, max_active: int = 128,
+          budget_bytes: int = 64 << 30, binding_fraction: float = 0.25,
+          seed: int = 1) -> Dict[str, Any]:
+    """Serving mix: a closed-loop capacity pass (all requests present at t=0),
+    open-loop passes with Poisson arrivals at each of load_factors x capacity
+    (p50/p99 latency at each; the headline fields are those at headline_load),
+    and one more pass at headline_load with a budget of binding_fraction of
+    the peak bytes that pass held, so that admission by memory footprint
+    binds and requests queue."""
     import workloads
 
     ex = GpuExecutor()
@@ -301,26 +307,42 @@ def bench(n_requests: int = 512, load_factor: float = 0.8, quantum: int = 25,
     res_closed = Scheduler(ex, budget_bytes, max_active, quantum).run(closed)
     cap_time = time.perf_counter() - t0
     capacity = n_requests / cap_time              # requests per second
-    rate = load_factor * capacity
-    reqs = workloads.serving_mix(n_requests, rate=rate, seed=seed)
-    sched = Scheduler(ex, budget_bytes, max_active, quantum)
-    res_open = sched.run(reqs)
-    s_open = summarize(res_open)
     s_closed = summarize(res_closed)
+
+    def open_pass(load: float, budget: int) -> Dict[str, Any]:
+        reqs = workloads.serving_mix(n_requests, rate=load * capacity, seed=seed)
+        sched = Scheduler(ex, budget, max_active, quantum)
+        s = summarize(sched.run(reqs))
+        return {"load_factor": load, "arrival_rate_per_s": load * capacity,
+                "p50_latency_s": s["p50_latency_s"], "p99_latency_s": s["p99_latency_s"],
+                "mean_latency_s": s["mean_latency_s"],
+                "aggregate_cell_updates_per_s": s["aggregate_cell_updates_per_s"],
+                "done": s["done"], "failed": s["failed"], "budget_bytes": budget,
+                "max_active": sched.stats["max_active"], "max_queue": sched.stats["max_queue"],
+                "max_bytes": sched.stats["max_bytes"]}
+
+    sweep = [open_pass(lf, budget_bytes) for lf in load_factors]
+    head = next((p for p in sweep if p["load_factor"] == headline_load), None)
+    if head is None:
+        head = open_pass(headline_load, budget_bytes)
+    largest = max(ex.footprint(r.workload) for r in reqs0)
+    binding = open_pass(headline_load, max(largest, int(binding_fraction * head["max_bytes"])))
     return {
         "requests": n_requests,
-        "arrival_rate_per_s": rate,
-        "load_factor": load_factor,
+        "arrival_rate_per_s": head["arrival_rate_per_s"],
+        "load_factor": headline_load,
         "closed_loop_capacity_req_per_s": capacity,
         "closed_loop_aggregate_cell_updates_per_s": s_closed["aggregate_cell_updates_per_s"],
-        "p50_latency_s": s_open["p50_latency_s"],
-        "p99_latency_s": s_open["p99_latency_s"],
-        "mean_latency_s": s_open["mean_latency_s"],
-        "aggregate_cell_updates_per_s": s_open["aggregate_cell_updates_per_s"],
-        "done": s_open["done"],
-        "failed": s_open["failed"],
+        "p50_latency_s": head["p50_latency_s"],
+        "p99_latency_s": head["p99_latency_s"],
+        "mean_latency_s": head["mean_latency_s"],
+        "aggregate_cell_updates_per_s": head["aggregate_cell_updates_per_s"],
+        "done": head["done"],
+        "failed": head["failed"],
         "quantum_steps": quantum,
-        "max_active": sched.stats["max_active"],
-        "max_queue": sched.stats["max_queue"],
+        "max_active": head["max_active"],
+        "max_queue": head["max_queue"],
         "budget_bytes": budget_bytes,
+        "load_sweep": sweep,
+        "binding_budget": binding,
     }

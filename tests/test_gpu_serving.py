@@ -12,8 +12,9 @@ pytestmark = pytest.mark.gpu
 
 
 def small_mix(n=12):
+    # the serving mix's full range of grid sizes: nx 64 .. 1024, nv 128 .. 2048
     reqs = workloads.serving_mix(n, rate=1e6, seed=7, steps_range=(20, 60),
-                                 nx_pow=(6, 8), nv_pow=(7, 9))
+                                 nx_pow=(6, 10), nv_pow=(7, 11))
     return reqs
 
 
@@ -26,6 +27,8 @@ def test_alone_equals_mix_bitwise(gpu):
     out = sched.run(reqs)
     assert all(o.status == "done" for o in out)
     assert sched.stats["max_queue"] > 0 and sched.stats["max_active"] >= 2
+    sizes = {(r.workload.nx, r.workload.nv) for r in reqs}
+    assert max(nx for nx, _ in sizes) >= 512 and max(nv for _, nv in sizes) >= 1024, sizes
     for o, r in zip(out, sorted(reqs, key=lambda r: r.rid)):
         s = vog.Sim(r.workload).init()
         s.step(r.workload.nsteps)
