@@ -297,6 +297,37 @@ struct Fft {
             });
         });
     }
+    // The same rows from the exact table entries r = 1, 2, 3 and 4, 8, 12
+    // only: entry r = 4a + b (a, b > 0) is formed as entry 4a times entry b,
+    // one rounding from two rounded factors.  6 of every 16 entries are
+    // read; for kernels whose time goes to fetching the table.
+    static __device__ __forceinline__ void load_rows_sparse(int t, const cx<T> *__restrict__ tw, Rows &rw) {
+        typedef T v2 __attribute__((ext_vector_type(2)));
+        typedef __attribute__((address_space(1))) const v2 gv2;
+        static_for<1, NPASS>([&](auto pc) {
+            constexpr int p = decltype(pc)::value;
+            constexpr int RP = radix(p), NS = ns(p);
+            static_for<0, R / RP>([&](auto uc) {
+                constexpr int u = decltype(uc)::value;
+                const int k = (t + u * TPF) & (NS - 1);
+                gv2 *row = (gv2 *)(tw + fft_tw_off(N, p) + 16 * k);
+                cx<T> *w = &rw.w[p - 1][u * RP];
+                w[0] = cx<T>{(T)1, (T)0};
+                static_for<1, RP>([&](auto rc) {
+                    constexpr int r = decltype(rc)::value;
+                    if constexpr (r < 4 || r % 4 == 0) {
+                        const v2 q = row[r];
+                        w[r] = cx<T>{q.x, q.y};
+                    }
+                });
+                static_for<5, RP>([&](auto rc) {
+                    constexpr int r = decltype(rc)::value;
+                    if constexpr (r % 4 != 0) w[r] = cmul(w[r - r % 4], w[r % 4]);
+                });
+            });
+        });
+    }
+
     template <int DIR>
     static __device__ __forceinline__ void run(cx<T> (&v)[R], int t, T *lre, T *lim, const Rows &rw) {
         static_for<0, NPASS>([&](auto pc) {

@@ -153,6 +153,20 @@ __device__ __forceinline__ long long uniform_ll(long long x) {
     return (long long)__builtin_bit_cast(uint64_t, uniform_d(__builtin_bit_cast(double, x)));
 }
 
+// The value of lane (lane ^ X) of the wave; X = 1, 2 by a DPP quad permute
+// of each 32-bit half, larger X through ds_bpermute.  All lanes active.
+template <int X>
+__device__ __forceinline__ double xor_lane(double x) {
+    if constexpr (X == 1 || X == 2) {
+        constexpr int ctrl = X == 1 ? 0xB1 : 0x4E;  // quad_perm [1,0,3,2], [2,3,0,1]
+        const uint64_t u = __builtin_bit_cast(uint64_t, x);
+        return __builtin_bit_cast(double, addr_join(__builtin_amdgcn_update_dpp(0, addr_lo(u), ctrl, 0xF, 0xF, false),
+                                                    __builtin_amdgcn_update_dpp(0, addr_hi(u), ctrl, 0xF, 0xF, false)));
+    } else {
+        return __shfl_xor(x, X, 64);
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
     if constexpr (sizeof(T) == 4)
@@ -462,8 +476,11 @@ __device__ __forceinline__ void sweep_body(const Batch &b, int sim, int blk, T *
     const double arg = b.a[sim];
     double EA = 0.0, EB = 0.0, betaA, betaB;
     if constexpr (KIND == 0) {
-        EA = S.Eeff[lineA];
-        EB = S.Eeff[lineB];
+        // E - E_app when the sim is driven, else E (the field solve then
+        // leaves Eeff unwritten)
+        const double *Ev = S.drv_sc ? S.Eeff : S.E;
+        EA = Ev[lineA];
+        EB = Ev[lineB];
         betaA = -arg * EA * S.inv_dv;
         betaB = -arg * EB * S.inv_dv;
     } else {
@@ -655,6 +672,12 @@ __device__ __forceinline__ void xsweep_body(const Batch &b, int sim, int hb, T *
     }
     __syncthreads();
 
+    // Rows of the tile back to f, and the tile's share of rho = int f dv: the
+    // FP64 sum of each row's B values in a fixed order (a thread's VEC values
+    // pairwise, then xor-shuffles over the VPR neighbouring lanes that hold
+    // the row, which leave the same sum in each of them) -> part[tile][row].
+    static_assert(C::TB % 64 == 0 && 64 % C::VPR == 0, "a row's vectors sit in one wave");
+    gmem<double> *part = as_global(S.part) + (size_t)tile * N;
     static_for<0, C::ITER>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
         const int q = tid + k * C::TB;
@@ -666,11 +689,16 @@ __device__ __forceinline__ void xsweep_body(const Batch &b, int sim, int hb, T *
             constexpr int el = decltype(ec)::value;
             e[el] = lds[(cv * C::VEC + el) * C::LDSP + pr];
         });
+        double sum;
         if constexpr (sizeof(T) == 4) {
             *reinterpret_cast<float4 *>(dst) = float4{e[0], e[1], e[2], e[3]};
+            sum = ((double)e[0] + (double)e[1]) + ((double)e[2] + (double)e[3]);
         } else {
             *reinterpret_cast<double2 *>(dst) = double2{e[0], e[1]};
+            sum = e[0] + e[1];
         }
+        static_for<0, ilog2(C::VPR)>([&](auto oc) { sum += xor_lane<1 << decltype(oc)::value>(sum); });
+        if (cv == 0) part[row] = sum;
     });
 }
 
@@ -679,6 +707,41 @@ __global__ __launch_bounds__((kFusedThreads<T, N>), (Fused<T, N>::WAVES)) void x
     __shared__ T smem[Fused<T, N>::SMEM];
     xsweep_body<T, N>(b, (int)blockIdx.y, (int)blockIdx.x, smem);
 }
+// ----------------------------------------------------------------- rho
+
+// rho_i = dv sum_p part[p][i] + feq_const for the kRhoCols columns
+// i = c0 .. c0 + kRhoCols - 1, by G * kRhoCols threads, in a fixed order: row
+// group g sums rows p = g, g + G, g + 2G, ... in turn, then the G group sums
+// are added pairwise.  Each group reads kRhoCols * 8 contiguous bytes per row;
+// a thread requests its rows DEPTH at a time before adding them.  red holds
+// G * kRhoCols doubles; all threads of the block must call it.
+template <int G, int DEPTH>
+__device__ __forceinline__ void rho_columns(const SimDev &S, int c0, double *red) {
+    static_assert((G & (G - 1)) == 0, "G is a power of two");
+    const int tx = threadIdx.x % kRhoCols, g = threadIdx.x / kRhoCols;
+    const int i = c0 + tx;
+    const int np = S.nparts, nx = S.nx;
+    const gmem<double> *part = as_global(S.part) + i;
+    double acc = 0.0;
+    if (i < nx) {
+        for (int p0 = g; p0 < np; p0 += DEPTH * G) {
+            double x[DEPTH];
+            static_for<0, DEPTH>([&](auto uc) {
+                constexpr int u = decltype(uc)::value;
+                const int p = p0 + u * G;
+                x[u] = p < np ? part[(size_t)p * nx] : 0.0;
+            });
+            static_for<0, DEPTH>([&](auto uc) { acc += x[decltype(uc)::value]; });
+        }
+    }
+    red[g * kRhoCols + tx] = acc;
+    for (int h = G / 2; h > 0; h /= 2) {
+        __syncthreads();
+        if (g < h) red[g * kRhoCols + tx] += red[(g + h) * kRhoCols + tx];
+    }
+    if (g == 0 && i < nx) as_global(S.rho)[i] = S.dv * red[tx] + S.feq_const;
+}
+
 // ----------------------------------------------------------------- field solve
 
 // One block per sim, TPF = N/16 threads (N = nx).  rho_hat = FFT(rho) gives
@@ -739,9 +802,10 @@ __device__ __forceinline__ void field_body(const Batch &b, int sim, double *smem
         constexpr int r = decltype(rc)::value;
         v[r] = cx<double>{rho[t + r * TPF], 0.0};
     });
-    // All twiddles of both transforms, requested together with rho.
+    // All twiddles of both transforms, requested together with rho (6 of
+    // every 16 table entries; the block is latency-bound on this fetch).
     typename F::Rows rows;
-    F::load_rows(t, tab, rows);
+    F::load_rows_sparse(t, tab, rows);
     // 1/(N k_m) for this thread's modes, requested now so that the loads
     // overlap the forward transform (Fourier solve only).
     double ik[R];
@@ -856,7 +920,7 @@ __device__ __forceinline__ void field_body(const Batch &b, int sim, double *smem
         const int j = t + TPF * F::kpos(i);
         const double ej = S.field_zero ? 0.0 : e[i];
         as_global(S.E)[j] = ej;
-        as_global(S.Eeff)[j] = ej - app[i];
+        if (S.drv_sc) as_global(S.Eeff)[j] = ej - app[i];
         e2 = fma(ej, ej, e2);
         finite = finite && isfinite(ej);
     });

@@ -61,27 +61,16 @@ __global__ __launch_bounds__(256) void transpose_kernel(const Batch b) {
     }
 }
 
-// rho_i = dv sum_p part[p][i] + feq_const, partial rows summed in order.
+// rho from the partial velocity sums, one block per 16 x-columns.
 __global__ __launch_bounds__(256) void rho_reduce_kernel(const Batch b) {
-    __shared__ double red[4][kTile];
+    __shared__ double red[256];
     const SimDev &S = *b.s[blockIdx.y];
-    const int i = blockIdx.x * kTile + (threadIdx.x & (kTile - 1));
-    const int ty = threadIdx.x / kTile;
-    if ((int)blockIdx.x * kTile >= S.nx) return;
-    const int np = S.nparts;
-    double acc = 0.0;
-    if (i < S.nx)
-        for (int p = ty; p < np; p += 4) acc += S.part[(size_t)p * S.nx + i];
-    red[ty][threadIdx.x & (kTile - 1)] = acc;
-    __syncthreads();
-    if (ty == 0 && i < S.nx) {
-        const int tx = threadIdx.x;
-        S.rho[i] = S.dv * (((red[0][tx] + red[1][tx]) + red[2][tx]) + red[3][tx]) + S.feq_const;
-    }
+    if ((int)blockIdx.x * kRhoCols >= S.nx) return;  // whole block
+    rho_columns<256 / kRhoCols, 16>(S, (int)blockIdx.x * kRhoCols, red);
 }
 
 void launch_rho_reduce(const Batch &b, int max_nx, hipStream_t st) {
-    hipLaunchKernelGGL(rho_reduce_kernel, dim3((max_nx + kTile - 1) / kTile, b.n), dim3(256), 0, st, b);
+    hipLaunchKernelGGL(rho_reduce_kernel, dim3((max_nx + kRhoCols - 1) / kRhoCols, b.n), dim3(256), 0, st, b);
 }
 
 void launch_transpose(bool fp64, bool to_v, const Batch &b, int max_tiles, hipStream_t st) {

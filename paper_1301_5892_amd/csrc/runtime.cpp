@@ -137,11 +137,18 @@ XMode xsweep_mode(const vog_config &c) {
 
 bool uses_fused_xsweep(const vog_config &c) { return xsweep_mode(c) != X_TRANSPOSED; }
 
+// Rows of velocity partial sums feeding rho: one per tile of the x-sweep on
+// the v-fastest layout, one per 64 velocities of the x -> v transpose.
+int rho_parts(const vog_config &c) {
+    return uses_fused_xsweep(c) ? c.nv / fused_lines_per_block(prec_fp64(c), c.nx)
+                                : (c.nv + kTile - 1) / kTile;
+}
+
 Layout layout_of(const vog_config &c) {
     const size_t es = prec_fp64(c) ? 8 : 4;
     const size_t cells = (size_t)c.nx * c.nv;
     const bool spline = c.interp == VOG_INTERP_BSPLINE;
-    const int nparts = (c.nv + kTile - 1) / kTile;
+    const int nparts = rho_parts(c);
     Layout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -498,11 +505,11 @@ int run_transpose(vog_sim *lead, const std::vector<vog_sim *> &sims, bool to_v) 
     return VOG_OK;
 }
 
-// rho from the partial sums of the x->v transpose.
+// rho from the partial velocity sums the x-advection left (tiled x-sweep or
+// x -> v transpose).
 int run_rho_reduce(vog_sim *lead, const std::vector<vog_sim *> &sims) {
     Group g;
-    for (vog_sim *s : sims)
-        if (!s->fused) g.sims.push_back(s);
+    g.sims = sims;
     return for_chunks(g, [&](const Batch &b, size_t base) {
         int maxnx = 0;
         for (int k = 0; k < b.n; ++k) maxnx = std::max(maxnx, g.sims[base + k]->cfg.nx);
@@ -619,17 +626,12 @@ int field_from_f(vog_sim *s) {
 int x_advection(vog_sim *lead, const std::vector<vog_sim *> &sims, const std::vector<double> &dt,
                 bool with_rho) {
     int rc;
-    std::vector<vog_sim *> fused;
-    for (vog_sim *s : sims)
-        if (s->fused) fused.push_back(s);
     if ((rc = run_sweep(lead, sims, dt, false, true)) != VOG_OK) return rc;
     if ((rc = run_transpose(lead, sims, false)) != VOG_OK) return rc;
     if ((rc = run_sweep(lead, sims, dt, false, false)) != VOG_OK) return rc;
     if ((rc = run_transpose(lead, sims, true)) != VOG_OK) return rc;
     if (!with_rho) return VOG_OK;
-    if ((rc = run_rho_reduce(lead, sims)) != VOG_OK) return rc;
-    if (!fused.empty() && (rc = run_rho_v(lead, fused)) != VOG_OK) return rc;
-    return VOG_OK;
+    return run_rho_reduce(lead, sims);
 }
 
 int device_guard(vog_sim *s) {
@@ -793,7 +795,7 @@ int vog_create(const vog_config *c, void *dev_workspace, size_t bytes, void *hip
     D.deltaf = prec_deltaf(*c);
     D.field_zero = c->field == VOG_FIELD_ZERO;
     D.n_feq = c->n_feq;
-    D.nparts = (nv + kTile - 1) / kTile;
+    D.nparts = rho_parts(*c);
     D.poisson = c->poisson;
     D.zero_mean = c->zero_mean;
     D.fp64 = fp64;
@@ -1077,8 +1079,11 @@ int vog_get_state(vog_sim *s, void *host_buf, size_t bytes) {
     memcpy(p + 8, &s->t, 8);
     HIP_TRY(hipMemcpyAsync(p + 16, s->host_dev.f, fb, hipMemcpyDeviceToHost, s->stream));
     HIP_TRY(hipMemcpyAsync(p + 16 + fb, s->host_dev.E, sizeof(double) * s->cfg.nx, hipMemcpyDeviceToHost, s->stream));
-    HIP_TRY(hipMemcpyAsync(p + 16 + fb + sizeof(double) * s->cfg.nx, s->host_dev.Eeff,
-                           sizeof(double) * s->cfg.nx, hipMemcpyDeviceToHost, s->stream));
+    // the advecting field: E - E_app for driven sims, E itself for the others
+    // (whose field solve leaves Eeff unwritten)
+    const double *eff = s->host_dev.drv_sc ? s->host_dev.Eeff : s->host_dev.E;
+    HIP_TRY(hipMemcpyAsync(p + 16 + fb + sizeof(double) * s->cfg.nx, eff, sizeof(double) * s->cfg.nx,
+                           hipMemcpyDeviceToHost, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
     return VOG_OK;
 }

@@ -13,6 +13,7 @@ constexpr int kTaps = 2 * kDMax + 2;     // 18 stencil offsets q = -8 .. 9
 constexpr int kMaxBatch = 64;            // sims per grouped launch
 constexpr int kRingCap = 4096;           // diagnostics records kept per sim
 constexpr int kTile = 64;                // transpose tile edge
+constexpr int kRhoCols = 16;             // x-columns per block of the partial-row reduction
 
 // Per-sim constants and device pointers, stored in the sim's workspace.
 // Written once at creation; kernels read it through a pointer.
@@ -21,7 +22,9 @@ struct SimDev {
     void *g;            // [nv][nx]  transposed copy used by the x-sweep
     double *E;          // [nx]      self-consistent field at the current time level
     double *Eeff;       // [nx]      advecting field E - E_app at the current time level
-    double *part;       // [nparts][nx] partial velocity sums, one row per 64 velocities
+                        //           (driven sims only; the others advect with E)
+    double *part;       // [nparts][nx] partial velocity sums: one row per tile of the
+                        // tiled x-sweep, or per 64 velocities of the x -> v transpose
     double *rho;        // [nx]      charge density rho_i = int f dv
     double *mom;        // [nx][2]   per-line moment sums
     const void *tw_x;   // FFT twiddle rows for length nx, storage precision (re, im)
