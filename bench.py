@@ -72,8 +72,8 @@ def kernel_source_hash() -> str:
     that an edit of the comments alone keeps a counter measurement valid."""
     import re
     h = hashlib.sha256()
-    for name in ("fft.hpp", "kernels.hpp", "sweep_f32.hip", "sweep_f64.hip", "xsweep.hip",
-                 "mixed.hip", "field.hip", "misc.hip", "vog_internal.hpp"):
+    for name in ("addr.hpp", "fft.hpp", "pair4096.hpp", "kernels.hpp", "sweep_f32.hip", "sweep_f64.hip",
+                 "xsweep.hip", "mixed.hip", "field.hip", "misc.hip", "vog_internal.hpp"):
         with open(os.path.join(ROOT, "paper_1301_5892_amd", "csrc", name)) as fh:
             text = fh.read()
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
@@ -294,10 +294,12 @@ def classify_kernel(name):
         return ("sweep_x" if name.split("(")[0].rstrip().endswith(", 1>") else "sweep_v", prec)
     if "transpose_kernel" in name:
         return ("transpose", prec)
-    if "rho_v_kernel" in name or "rho_reduce_kernel" in name:
+    if "rho_reduce_kernel" in name:
         return ("rho_reduce", prec)
+    if "rho_v_kernel" in name:  # rho straight from f: initial state, vog_sweep field recompute
+        return ("rho_v", prec)
     if "field_kernel" in name:
-        return ("field", "fp64")
+        return ("field", None)
     if "moments" in name:
         return ("moments", prec)
     return None
@@ -316,13 +318,34 @@ def _csv_rows(folder, suffix):
     return rows
 
 
+def _labelled(rows):
+    """(row, kind, precision) for the libvog and copy dispatches among rows,
+    in dispatch order.  Kernels whose name does not carry the storage
+    precision (the partial-row reduce, the field solve) take that of the
+    sweep launched before them: the bench runs one sim at a time."""
+    out, last = [], None
+    for r in sorted(rows, key=lambda r: int(r["dispatch_id"])):
+        c = classify_kernel(r["kernel_name"])
+        if c is None:
+            continue
+        kind, prec = c
+        if kind != "copy":
+            if prec in ("fp32_deltaf", "fp64_plain"):
+                last = prec
+            else:
+                prec = last
+        out.append((r, kind, prec))
+    return out
+
+
 def _counter_per_kernel(folder, counter=None):
-    """kernel name -> list of per-dispatch values of one counter (all rows when
-    the file holds a single counter)."""
+    """(kernel name, kind, precision) -> list of per-dispatch values of one
+    counter (all rows when the file holds a single counter)."""
+    rows = [r for r in _csv_rows(folder, "counter_collection.csv")
+            if counter is None or r["counter_name"] == counter]
     out = {}
-    for r in _csv_rows(folder, "counter_collection.csv"):
-        if counter is None or r["counter_name"] == counter:
-            out.setdefault(r["kernel_name"], []).append(float(r["counter_value"]))
+    for r, kind, prec in _labelled(rows):
+        out.setdefault((r["kernel_name"], kind, prec), []).append(float(r["counter_value"]))
     return out
 
 
@@ -349,25 +372,27 @@ def summarize_rocprof(folder, wname):
     cmds = {k: v.format(out="$OUT", root="$REPO") for k, v in PROFILE_COMMANDS.items()}
     bench_rec = _last_json(os.path.join(folder, "kt.log"))
 
-    # kernel trace statistics
-    stats = _csv_rows(os.path.join(folder, "kt"), "kernel_stats.csv")
+    # kernel trace statistics, per kernel and storage precision of the sim
+    trace = _labelled(_csv_rows(os.path.join(folder, "kt"), "kernel_trace.csv"))
     lines = [f"# Kernel trace, {wname}", "",
              "Command (from /tmp, TMPDIR=/tmp; $REPO is the repository root, $OUT the output "
              "folder):", "", "```", cmds["kt"], "```", "",
+             "Per-dispatch durations from the trace; precision is that of the sim (the field "
+             "solve computes in FP64 for both).", "",
              "| kernel | kind | precision | calls | avg us | min us | max us | % time |",
              "|---|---|---|---|---|---|---|---|"]
+    groups = {}
+    for r, kind, prec in trace:
+        dur = (int(r["end_timestamp"]) - int(r["start_timestamp"])) / 1e3
+        groups.setdefault((r["kernel_name"].split("(")[0], kind, prec), []).append(dur)
+    total = sum(sum(v) for v in groups.values()) or 1.0
     trace_avg = {}
-    for r in sorted(stats, key=lambda r: -float(r.get("totaldurationns", 0))):
-        name = r["name"]
-        c = classify_kernel(name)
-        if c is None:
-            continue
-        avg = float(r["averagens"]) / 1e3
-        if c[0] != "copy":
-            trace_avg[c] = avg
-        lines.append(f"| `{name.split('(')[0]}` | {c[0]} | {c[1] or '-'} | {r['calls']} | "
-                     f"{avg:.2f} | {float(r['minns']) / 1e3:.2f} | {float(r['maxns']) / 1e3:.2f} | "
-                     f"{float(r['percentage']):.1f} |")
+    for (name, kind, prec), d in sorted(groups.items(), key=lambda kv: -sum(kv[1])):
+        avg = sum(d) / len(d)
+        if kind != "copy":
+            trace_avg[(kind, prec)] = avg
+        lines.append(f"| `{name}` | {kind} | {prec or '-'} | {len(d)} | {avg:.2f} | {min(d):.2f} | "
+                     f"{max(d):.2f} | {100 * sum(d) / total:.1f} |")
     if bench_rec:
         lines += ["", "HIP-event averages the bench printed in the same run (ms per launch):", ""]
         for label, rf in (("fp32_deltaf", bench_rec.get("roofline")),
@@ -385,8 +410,8 @@ def summarize_rocprof(folder, wname):
     fetch = _counter_per_kernel(os.path.join(folder, "fetch"))
     write = _counter_per_kernel(os.path.join(folder, "write"))
     cal_kib = COPY_CALIBRATION_BYTES / 1024.0
-    copy_f = max((max(v) for k, v in fetch.items() if "copyBuffer" in k), default=None)
-    copy_w = max((max(v) for k, v in write.items() if "copyBuffer" in k), default=None)
+    copy_f = max((max(v) for k, v in fetch.items() if k[1] == "copy"), default=None)
+    copy_w = max((max(v) for k, v in write.items() if k[1] == "copy"), default=None)
     if not copy_f or not copy_w:
         raise SystemExit("no copy kernel in the counter output")
     kf, kw = cal_kib / copy_f, cal_kib / copy_w
@@ -410,26 +435,40 @@ def summarize_rocprof(folder, wname):
     es = {"fp32_deltaf": 4, "fp64_plain": 8}
     import workloads
     wl = {x.name: x for x in workloads.all_named()}.get(wname)
-    for name in sorted(set(fetch) & set(write)):
-        c = classify_kernel(name)
-        if c is None or c[0] == "copy":
+    per_launch = {}
+    for key in sorted(set(fetch) & set(write), key=lambda k: (str(k[2]), k[1], k[0])):
+        name, kind, prec = key
+        if kind == "copy":
             continue
-        f_avg = sum(fetch[name]) / len(fetch[name])
-        w_avg = sum(write[name]) / len(write[name])
+        f_avg = sum(fetch[key]) / len(fetch[key])
+        w_avg = sum(write[key]) / len(write[key])
         rd, wr = f_avg * 1024 * kf, w_avg * 1024 * kw
         alg = None
-        if wl and c[1] in es:
-            # a sweep reads and writes f once; the velocity sums read it once
-            alg = {"sweep_v": 2, "sweep_x": 2, "rho_reduce": 1}.get(c[0], 0) * es[c[1]] * wl.cells
-            alg = alg or None
-        lines.append(f"| `{name.split('(')[0]}` | {c[0]} | {c[1] or '-'} | {len(fetch[name])} | "
+        if wl and prec in es:
+            # a sweep reads and writes f once; the other kernels' bytes are
+            # overhead on top of the step's algorithmic traffic
+            alg = {"sweep_v": 2, "sweep_x": 2}.get(kind, 0) * es[prec] * wl.cells or None
+        lines.append(f"| `{name.split('(')[0]}` | {kind} | {prec or '-'} | {len(fetch[key])} | "
                      f"{f_avg:.0f} | {w_avg:.0f} | {rd / 1e6:.2f} | {wr / 1e6:.2f} | "
                      f"{'-' if alg is None else f'{alg / 1e6:.2f}'} |")
-        if c[1] in es:
-            table[f"{c[0]}/{wname}/{c[1]}"] = {
+        if prec in es:
+            per_launch[(kind, prec)] = rd + wr
+            table[f"{kind}/{wname}/{prec}"] = {
                 "kernel": name.split("(")[0], "kernel_source_hash": src_hash,
                 "fetch_bytes": rd, "write_bytes": wr, "bytes_per_launch": rd + wr,
                 "fetch_scale": kf, "write_scale": kw}
+    if wl:
+        lines += ["", "Per Strang step (two v-sweeps, one x-sweep, the partial-row reduce and the "
+                  "field solve) against the algorithmic 3 x (read + write of f):", ""]
+        for prec, e in es.items():
+            kinds = {k: v for (k, p), v in per_launch.items() if p == prec}
+            if "sweep_v" not in kinds or "sweep_x" not in kinds:
+                continue
+            per_step = {"sweep_v": 2, "sweep_x": 1, "transpose": 2, "rho_reduce": 1, "field": 1}
+            step = sum(per_step.get(k, 0) * v for k, v in kinds.items())
+            alg = 6 * e * wl.cells
+            lines.append(f"- {prec}: {step / 1e6:.1f} MB measured, {alg / 1e6:.1f} MB algorithmic "
+                         f"({6 * e} B per cell): {step / alg:.3f}x")
     with open(os.path.join(prof_dir, f"hbm_traffic_{wname}.md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
     with open(table_path, "w") as fh:
@@ -454,14 +493,14 @@ def summarize_rocprof(folder, wname):
                  "4 SIMDs per CU.", "",
                  "| kernel | kind | precision | VALU instr (wave) | VALU busy | LDS instr (wave) | "
                  "LDS wait / wave-cycles |", "|---|---|---|---|---|---|---|"]
-        for name in sorted(per["SQ_INSTS_VALU"]):
-            c = classify_kernel(name)
-            if c is None or c[0] == "copy":
+        for key in sorted(per["SQ_INSTS_VALU"], key=lambda k: (str(k[2]), k[1], k[0])):
+            name, kind, prec = key
+            if kind == "copy":
                 continue
-            avg = {n: (sum(per[n].get(name, [0])) / max(len(per[n].get(name, [])), 1)) for n in names}
+            avg = {n: (sum(per[n].get(key, [0])) / max(len(per[n].get(key, [])), 1)) for n in names}
             busy = avg["SQ_ACTIVE_INST_VALU"] / max(avg["SQ_BUSY_CU_CYCLES"], 1)
             ldsw = avg["SQ_WAIT_INST_LDS"] / max(avg["SQ_WAVE_CYCLES"], 1)
-            lines.append(f"| `{name.split('(')[0]}` | {c[0]} | {c[1] or '-'} | "
+            lines.append(f"| `{name.split('(')[0]}` | {kind} | {prec or '-'} | "
                          f"{avg['SQ_INSTS_VALU']:.3g} | {busy:.2f} | {avg['SQ_INSTS_LDS']:.3g} | "
                          f"{ldsw:.3f} |")
         with open(os.path.join(prof_dir, f"valu_{wname}.md"), "w") as fh:
