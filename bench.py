@@ -181,10 +181,14 @@ def roofline_for(w, precision, prof, steps):
     ms, n = prof[kind]
     avg_s = ms / 1e3 / max(n, 1)
     cells = w.nx * w.nv
-    line = {"sweep_v": w.nv, "sweep_x": w.nx}.get(kind)
-    # Algorithmic bytes: the sweep reads and writes f once; a transpose also
-    # moves f once each way (not algorithmic for the method, reported as is).
-    bytes_per_launch = 2 * es * cells
+    line = {"sweep_v": w.nv, "sweep_vv": w.nv, "sweep_x": w.nx}.get(kind)
+    # Algorithmic bytes: a sweep reads and writes f once (a transpose also
+    # moves f once each way: not algorithmic for the method, reported as is).
+    # A sweep_vv launch carries two v half-steps (the closing one of a step
+    # and the opening one of the next), so two sweeps' worth, while it moves
+    # f once each way itself.
+    sweeps = 2 if kind == "sweep_vv" else 1
+    bytes_per_launch = sweeps * 2 * es * cells
     hbm = {"bound": "hbm", "achieved": bytes_per_launch / avg_s / 1e9, "peak": HBM_PEAK_GBS,
            "unit": "GB/s"}
     hbm["frac"] = hbm["achieved"] / hbm["peak"]
@@ -193,10 +197,11 @@ def roofline_for(w, precision, prof, steps):
     hbm["avg_launch_ms"] = avg_s * 1e3
     hbm["launches"] = n
     hbm["bytes_per_launch"] = bytes_per_launch
+    hbm["sweeps_per_launch"] = sweeps
     if line:
         # The paper's real-data operation count per advected element,
         # 5 log2(N) + 3 (FFT pair plus complex multiply).
-        flops = (5 * math.log2(line) + 3) * cells
+        flops = sweeps * (5 * math.log2(line) + 3) * cells
         peak = FP32_VALU_PEAK_TFLOPS if es == 4 else FP64_VALU_PEAK_TFLOPS
         ach = flops / avg_s / 1e12
         hbm["alu_view"] = {"achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
@@ -291,7 +296,8 @@ def classify_kernel(name):
     if "xsweep_fused_kernel" in name:
         return ("sweep_x", prec)
     if "sweep_kernel" in name:
-        return ("sweep_x" if name.split("(")[0].rstrip().endswith(", 1>") else "sweep_v", prec)
+        tail = name.split("(")[0].rstrip()
+        return ({", 1>": "sweep_x", ", 2>": "sweep_vv"}.get(tail[-4:], "sweep_v"), prec)
     if "transpose_kernel" in name:
         return ("transpose", prec)
     if "rho_reduce_kernel" in name:
@@ -447,7 +453,7 @@ def summarize_rocprof(folder, wname):
         if wl and prec in es:
             # a sweep reads and writes f once; the other kernels' bytes are
             # overhead on top of the step's algorithmic traffic
-            alg = {"sweep_v": 2, "sweep_x": 2}.get(kind, 0) * es[prec] * wl.cells or None
+            alg = {"sweep_v": 2, "sweep_x": 2, "sweep_vv": 4}.get(kind, 0) * es[prec] * wl.cells or None
         lines.append(f"| `{name.split('(')[0]}` | {kind} | {prec or '-'} | {len(fetch[key])} | "
                      f"{f_avg:.0f} | {w_avg:.0f} | {rd / 1e6:.2f} | {wr / 1e6:.2f} | "
                      f"{'-' if alg is None else f'{alg / 1e6:.2f}'} |")

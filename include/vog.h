@@ -260,10 +260,11 @@ const char *vog_last_error(void);
 /* Kernel timing with HIP events recorded on the sim's stream around every
  * launch of the sim (or of a batch led by it).  Kinds: 0 v-sweep, 1 x-sweep,
  * 2 transpose v->x, 3 transpose x->v with rho partial sums, 4 field solve,
- * 5 moments, 6 rho reduction.  vog_profile_read synchronises and returns, per
- * kind, the summed milliseconds and the number of launches since profiling
- * was enabled. */
-#define VOG_NUM_KINDS 7
+ * 5 moments, 6 rho reduction, 7 two v half-steps in one launch (the closing
+ * half-step of a step and the opening one of the next, Section 1.1).
+ * vog_profile_read synchronises and returns, per kind, the summed
+ * milliseconds and the number of launches since profiling was enabled. */
+#define VOG_NUM_KINDS 8
 int vog_profile_enable(vog_sim *sim, int on);
 int vog_profile_read(vog_sim *sim, double *ms, int64_t *launches, int nkinds);
 

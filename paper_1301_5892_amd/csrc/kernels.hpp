@@ -230,15 +230,15 @@ __device__ __forceinline__ void deltaf_source(const SimDev &S, double tauE, int 
     }
 }
 
-// Stores a transformed line pair: out(k) (k a compile-time index) is the
+// Emits a transformed line pair: out(k) (k a compile-time index) is the
 // result at unshifted position t + TPF k, lines A (real part) and B
 // (imaginary part).  Unshifted index j goes to line position (j - b) mod N;
-// pos[k] is the byte offset of position (p0 + k TPF) mod N in a line.
-// VSWEEP: adds the delta-f source (Section 3.1) with tau E of each line.
-template <typename T, int N, int R, int TPF, bool VSWEEP, typename Out>
-__device__ __forceinline__ void store_pair(const SimDev &S, double tauEA, double tauEB, long long bA,
-                                           long long bB, int t, __amdgpu_buffer_rsrc_t rA, unsigned oA,
-                                           __amdgpu_buffer_rsrc_t rB, unsigned oB, Out &&out) {
+// sinkA(pos, x) and sinkB(pos, x) receive each value x with the byte offset
+// pos of its position in the line.  VSWEEP: adds the delta-f source
+// (Section 3.1) with tau E of each line.
+template <typename T, int N, int R, int TPF, bool VSWEEP, typename Out, typename SinkA, typename SinkB>
+__device__ __forceinline__ void emit_pair(const SimDev &S, double tauEA, double tauEB, long long bA,
+                                          long long bB, int t, Out &&out, SinkA &&sinkA, SinkB &&sinkB) {
     constexpr unsigned LB = N * sizeof(T);  // bytes per line
     const int p0A = (t - (int)(bA & (N - 1))) & (N - 1);
     const int p0B = (t - (int)(bB & (N - 1))) & (N - 1);
@@ -257,13 +257,13 @@ __device__ __forceinline__ void store_pair(const SimDev &S, double tauEA, double
             deltaf_source<T, N, R, TPF>(S, tauEA, p0A, pos, src);
             static_for<0, R>([&](auto kc) {
                 constexpr int k = decltype(kc)::value;
-                buf_store<T>(out(kc).re + src[k], rA, oA + pos[k], 0);
+                sinkA(pos[k], out(kc).re + src[k]);
             });
             positions(p0B, pos);
             deltaf_source<T, N, R, TPF>(S, tauEB, p0B, pos, src);
             static_for<0, R>([&](auto kc) {
                 constexpr int k = decltype(kc)::value;
-                buf_store<T>(out(kc).im + src[k], rB, oB + pos[k], 0);
+                sinkB(pos[k], out(kc).im + src[k]);
             });
             return;
         }
@@ -271,13 +271,23 @@ __device__ __forceinline__ void store_pair(const SimDev &S, double tauEA, double
     positions(p0A, pos);
     static_for<0, R>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
-        buf_store<T>(out(kc).re, rA, oA + pos[k], 0);
+        sinkA(pos[k], out(kc).re);
     });
     positions(p0B, pos);
     static_for<0, R>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
-        buf_store<T>(out(kc).im, rB, oB + pos[k], 0);
+        sinkB(pos[k], out(kc).im);
     });
+}
+
+// emit_pair into f: lines A and B through their descriptors and offsets.
+template <typename T, int N, int R, int TPF, bool VSWEEP, typename Out>
+__device__ __forceinline__ void store_pair(const SimDev &S, double tauEA, double tauEB, long long bA,
+                                           long long bB, int t, __amdgpu_buffer_rsrc_t rA, unsigned oA,
+                                           __amdgpu_buffer_rsrc_t rB, unsigned oB, Out &&out) {
+    emit_pair<T, N, R, TPF, VSWEEP>(
+        S, tauEA, tauEB, bA, bB, t, out, [&](unsigned pos, T x) { buf_store<T>(x, rA, oA + pos, 0); },
+        [&](unsigned pos, T x) { buf_store<T>(x, rB, oB + pos, 0); });
 }
 
 // Weights of a line pair for its fractional shifts sA, sB, combined for the
@@ -416,7 +426,11 @@ __device__ __forceinline__ void pair_transform(cx<T> (&v)[R], cx<T> (&Y)[R], int
 
 // KIND 0: v-advection by tau = b.a[sim] with field E (lines are x-columns of
 // f, length nv).  KIND 1: x-advection by dt = b.a[sim] (lines are v-rows of
-// the transposed copy g, length nx).
+// the transposed copy g, length nx).  KIND 2: two v-advections by tau in a
+// row with the same E (the closing half step of one Strang step and the
+// opening one of the next): the first result, source term included, goes
+// through LDS instead of f, in the same FP32 or FP64 values a store and a
+// reload would give.
 //
 // Two real lines A, B are packed as z = uA + i uB and transformed together.
 // With beta = b + s (b integer, s in [0,1)), the circulant A of Section 1.2 is
@@ -441,7 +455,8 @@ __device__ __forceinline__ void sweep_body(const Batch &b, int sim, int blk, T *
     T(*wsh)[2][kTaps] = reinterpret_cast<T(*)[2][kTaps]>(smem + PPB * 2 * F::LDSN);
 
     const SimDev &S = *b.s[sim];
-    const int nlines = KIND == 0 ? S.nx : S.nv;
+    constexpr bool VS = KIND != 1;  // a v-sweep
+    const int nlines = VS ? S.nx : S.nv;
     const int npairs = nlines >> 1;
     if (blk * PPB >= npairs) return;  // whole block idle
 
@@ -453,12 +468,12 @@ __device__ __forceinline__ void sweep_body(const Batch &b, int sim, int blk, T *
     const int lineB = lineA + 1;
     T *lre = lds[slot][0];
     T *lim = lds[slot][1];
-    const cx<T> *tw = (const cx<T> *)(KIND == 0 ? S.tw_v : S.tw_x);
-    const cx<T> *eps = (const cx<T> *)(KIND == 0 ? S.eps_v : S.eps_x) + t * kEpsRow;
+    const cx<T> *tw = (const cx<T> *)(VS ? S.tw_v : S.tw_x);
+    const cx<T> *eps = (const cx<T> *)(VS ? S.eps_v : S.eps_x) + t * kEpsRow;
     // One pair per block: a descriptor per line (uniform base).  Otherwise one
     // for the sim's array, with the line's offset in the byte offset.
     constexpr unsigned LB = N * sizeof(T);  // bytes per line
-    const T *data = (const T *)(KIND == 0 ? S.f : S.g);
+    const T *data = (const T *)(VS ? S.f : S.g);
     __amdgpu_buffer_rsrc_t rA, rB;
     unsigned oA, oB;
     if constexpr (PPB == 1) {
@@ -475,7 +490,7 @@ __device__ __forceinline__ void sweep_body(const Batch &b, int sim, int blk, T *
     // beta = -v_j dt / dx.
     const double arg = b.a[sim];
     double EA = 0.0, EB = 0.0, betaA, betaB;
-    if constexpr (KIND == 0) {
+    if constexpr (VS) {
         // E - E_app when the sim is driven, else E (the field solve then
         // leaves Eeff unwritten)
         const double *Ev = S.drv_sc ? S.Eeff : S.E;
@@ -519,36 +534,62 @@ __device__ __forceinline__ void sweep_body(const Batch &b, int sim, int blk, T *
 
     // Y[i] holds the result at position t + TPF kpos(i) (kP4k: kpos(i) = i)
     cx<T> Y[R];
-    const T *iden = (const T *)(KIND == 0 ? S.iden_v : S.iden_x);
-    if constexpr (kP4k) {
-        const cx<T> *eps0 = (const cx<T> *)(KIND == 0 ? S.eps_v : S.eps_x);
-        {
-            cx<T> w[16];
-            p4k_col_row<T>(tw, t, w);
-            p4k_fwd_col<T>(v, t, lre, lim, w);
+    const T *iden = (const T *)(VS ? S.iden_v : S.iden_x);
+    // (KIND 2 gives the second transform opaque copies of the tables and of
+    // t, so that it reads the tables and forms its LDS addresses again
+    // instead of keeping the first transform's values live)
+    auto transform = [&](const cx<T> *twp, const cx<T> *epsp, int tt) {
+        if constexpr (kP4k) {
+            const cx<T> *eps0 = epsp - tt * kEpsRow;
+            {
+                cx<T> w[16];
+                p4k_col_row<T>(twp, tt, w);
+                p4k_fwd_col<T>(v, tt, lre, lim, w);
+            }
+            __syncthreads();
+            p4k_lanes<T>(tt >> 6, tt & 63, lre, lim, LoadRows<T>{twp, eps0}, wsh[0][0], iden);
+            __syncthreads();
+            {
+                cx<T> w[16];
+                p4k_col_row<T>(opaque(twp), tt, w);  // re-read, not kept live
+                p4k_inv_col<T>(Y, tt, lre, lim, w);
+            }
+        } else {
+            // a line pair of at most 1024 points is one wave's contiguous lanes
+            pair_transform<T, N, (sizeof(T) == 8), (TPF <= 64)>(v, Y, tt, lre, lim, twp, epsp, wsh[slot][0],
+                                                                wsh[slot][1], iden);
         }
-        __syncthreads();
-        p4k_lanes<T>(t >> 6, t & 63, lre, lim, LoadRows<T>{tw, eps0}, wsh[0][0], iden);
-        __syncthreads();
-        {
-            cx<T> w[16];
-            p4k_col_row<T>(opaque(tw), t, w);  // re-read, not kept live
-            p4k_inv_col<T>(Y, t, lre, lim, w);
-        }
-    } else {
-        // a line pair of at most 1024 points is one wave's contiguous lanes
-        pair_transform<T, N, (sizeof(T) == 8), (TPF <= 64)>(v, Y, t, lre, lim, tw, eps, wsh[slot][0],
-                                                            wsh[slot][1], iden);
-    }
+    };
     auto out = [&](auto kc) -> const cx<T> & {
         constexpr int k = decltype(kc)::value;
         if constexpr (kP4k) return Y[k];
         else return Y[F::kinv(k)];
     };
 
+    transform(tw, eps, t);
+    if constexpr (KIND == 2) {
+        // The first half step's result to LDS at its positions in the line,
+        // then back in the load layout v[r] = z[t + r TPF] for the second.
+        // The pair's threads are one wave for lines of at most 1024 points.
+        constexpr bool WAVE = !kP4k && TPF <= 64;
+        xsync<WAVE>();
+        emit_pair<T, N, R, TPF, true>(
+            S, arg * EA, arg * EB, bA, bB, t, out,
+            [&](unsigned pos, T x) { lre[F::pad((int)(pos / sizeof(T)))] = x; },
+            [&](unsigned pos, T x) { lim[F::pad((int)(pos / sizeof(T)))] = x; });
+        xsync<WAVE>();
+        static_for<0, R>([&](auto rc) {
+            constexpr int r = decltype(rc)::value;
+            const int i = F::pad(t + r * TPF);
+            v[r] = cx<T>{lre[i], lim[i]};
+        });
+        if constexpr (kP4k) __syncthreads();  // reads done before the digit transform writes
+        transform(opaque(tw), opaque(eps), opaque(t));
+    }
+
     if (!active) return;
 
-    store_pair<T, N, R, TPF, KIND == 0>(S, arg * EA, arg * EB, bA, bB, t, rA, oA, rB, oB, out);
+    store_pair<T, N, R, TPF, VS>(S, arg * EA, arg * EB, bA, bB, t, rA, oA, rB, oB, out);
 }
 
 // One line length per launch: blockIdx.y = sim, blockIdx.x = block.

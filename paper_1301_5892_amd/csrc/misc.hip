@@ -6,13 +6,13 @@
 
 namespace vog {
 
-LaunchFn sweep_launcher_f32(int n, bool vsweep);
-LaunchFn sweep_launcher_f64(int n, bool vsweep);
+LaunchFn sweep_launcher_f32(int n, int kind);
+LaunchFn sweep_launcher_f64(int n, int kind);
 
-LaunchFn sweep_launcher(bool fp64, int n, bool vsweep) {
+LaunchFn sweep_launcher(bool fp64, int n, int kind) {
     const int logn = ilog2(n);
-    if (n < VOG_MIN_N || n > VOG_MAX_N || (1 << logn) != n) return nullptr;
-    return fp64 ? sweep_launcher_f64(n, vsweep) : sweep_launcher_f32(n, vsweep);
+    if (n < VOG_MIN_N || n > VOG_MAX_N || (1 << logn) != n || kind < 0 || kind > 2) return nullptr;
+    return fp64 ? sweep_launcher_f64(n, kind) : sweep_launcher_f32(n, kind);
 }
 
 // ----------------------------------------------------------------- transpose

@@ -7,19 +7,21 @@ namespace vog {
 // FP32 v-sweeps of sims with lines of 64 .. 4096 points in one launch: every
 // block runs the body of its sim's line length (each block carries 8192
 // values whatever the length).
+// KIND 0: one v half-step; KIND 2: two in a row (sweep_body).
+template <int KIND>
 __global__ __launch_bounds__(256, 3) void sweep_v_mixed_kernel(const Batch b, const BlockMap m) {
     __shared__ float smem[Sweep<float, 64>::SMEM];  // the largest of 64 .. 4096
     const int bid = (int)blockIdx.x;
     const int k = mixed_sim(b, m, bid);
     const int blk = bid - m.first[k];
     switch (m.lgn[k]) {
-    case 6: sweep_body<float, 64, 0>(b, k, blk, smem); break;
-    case 7: sweep_body<float, 128, 0>(b, k, blk, smem); break;
-    case 8: sweep_body<float, 256, 0>(b, k, blk, smem); break;
-    case 9: sweep_body<float, 512, 0>(b, k, blk, smem); break;
-    case 10: sweep_body<float, 1024, 0>(b, k, blk, smem); break;
-    case 11: sweep_body<float, 2048, 0>(b, k, blk, smem); break;
-    case 12: sweep_body<float, 4096, 0>(b, k, blk, smem); break;
+    case 6: sweep_body<float, 64, KIND>(b, k, blk, smem); break;
+    case 7: sweep_body<float, 128, KIND>(b, k, blk, smem); break;
+    case 8: sweep_body<float, 256, KIND>(b, k, blk, smem); break;
+    case 9: sweep_body<float, 512, KIND>(b, k, blk, smem); break;
+    case 10: sweep_body<float, 1024, KIND>(b, k, blk, smem); break;
+    case 11: sweep_body<float, 2048, KIND>(b, k, blk, smem); break;
+    case 12: sweep_body<float, 4096, KIND>(b, k, blk, smem); break;
     default: break;
     }
 }
@@ -73,9 +75,10 @@ int sweep_blocks_mixed(bool vsweep, int n, int lines) {
     return (tiles + 7) / 8 * 8;
 }
 
-void launch_sweep_mixed(bool vsweep, const Batch &b, const BlockMap &m, hipStream_t st) {
+void launch_sweep_mixed(int kind, const Batch &b, const BlockMap &m, hipStream_t st) {
     const int blocks = m.first[b.n];
-    if (vsweep) hipLaunchKernelGGL(sweep_v_mixed_kernel, dim3(blocks), dim3(256), 0, st, b, m);
+    if (kind == 0) hipLaunchKernelGGL(sweep_v_mixed_kernel<0>, dim3(blocks), dim3(256), 0, st, b, m);
+    else if (kind == 2) hipLaunchKernelGGL(sweep_v_mixed_kernel<2>, dim3(blocks), dim3(256), 0, st, b, m);
     else hipLaunchKernelGGL(xsweep_mixed_kernel, dim3(blocks), dim3(256), 0, st, b, m);
 }
 

@@ -406,11 +406,33 @@ int check_launch() {
 }
 
 // Sweeps of all sims (tau or dt per sim).  vsweep: v-advection on the
-// v-fastest layout.  Otherwise x-advection: fused = true selects the sims
-// whose x-sweep runs on the v-fastest layout, fused = false the others (which
-// work on the transposed copy).
+// v-fastest layout (twice: two v-advections by tau in a row, one launch).
+// Otherwise x-advection: fused = true selects the sims whose x-sweep runs on
+// the v-fastest layout, fused = false the others (which work on the
+// transposed copy).
 int run_sweep(vog_sim *lead, const std::vector<vog_sim *> &sims, const std::vector<double> &arg,
-              bool vsweep, bool fused = false) {
+              bool vsweep, bool fused = false, bool twice = false) {
+    if (twice) {
+        // FP64 4096-point v-lines: the two-in-one kernel needs more than 256
+        // VGPRs (one wave per SIMD instead of two), so those sims take two
+        // launches of the single-step kernel, which give the same values.
+        std::vector<vog_sim *> split, rest;
+        std::vector<double> as, ar;
+        for (size_t k = 0; k < sims.size(); ++k) {
+            const bool sp = sims[k]->fp64 && sims[k]->cfg.nv == 4096;
+            (sp ? split : rest).push_back(sims[k]);
+            (sp ? as : ar).push_back(arg[k]);
+        }
+        if (!split.empty()) {
+            for (int i = 0; i < 2; ++i) {
+                const int rc = run_sweep(lead, split, as, true);
+                if (rc != VOG_OK) return rc;
+            }
+            return rest.empty() ? VOG_OK : run_sweep(lead, rest, ar, true, false, true);
+        }
+    }
+    const int vkind = twice ? 2 : 0;                     // sweep kind of a v-sweep launch
+    const Kind pkind = twice ? K_SWEEP_VV : K_SWEEP_V;  // its profile kind
     std::map<std::pair<int, int>, Group> groups;  // (fp64, line length)
     for (size_t k = 0; k < sims.size(); ++k) {
         vog_sim *s = sims[k];
@@ -451,8 +473,8 @@ int run_sweep(vog_sim *lead, const std::vector<vog_sim *> &sims, const std::vect
                 m.first[k + 1] = m.first[k] + sweep_blocks_mixed(vsweep, n, vsweep ? s->cfg.nx : s->cfg.nv);
             }
             EventPair *p;
-            prof_begin(lead, vsweep ? K_SWEEP_V : K_SWEEP_X, &p);
-            launch_sweep_mixed(vsweep, b, m, lead->stream);
+            prof_begin(lead, vsweep ? pkind : K_SWEEP_X, &p);
+            launch_sweep_mixed(vsweep ? vkind : 1, b, m, lead->stream);
             prof_end(lead, p);
             return check_launch();
         });
@@ -461,9 +483,9 @@ int run_sweep(vog_sim *lead, const std::vector<vog_sim *> &sims, const std::vect
     for (auto &kv : groups) {
         const bool fp64 = (kv.first.first & 1) != 0;
         const int xmode = kv.first.first / 2;
-        LaunchFn fn = vsweep             ? sweep_launcher(fp64, kv.first.second, true)
+        LaunchFn fn = vsweep             ? sweep_launcher(fp64, kv.first.second, vkind)
                       : xmode == X_TILED ? fused_xsweep_launcher(fp64, kv.first.second)
-                                         : sweep_launcher(fp64, kv.first.second, false);
+                                         : sweep_launcher(fp64, kv.first.second, 1);
         if (!fn) return fail(VOG_EINVAL, "no sweep kernel for this line length");
         int rc = for_chunks(kv.second, [&](const Batch &b, size_t base) {
             int maxl = 0;
@@ -472,7 +494,7 @@ int run_sweep(vog_sim *lead, const std::vector<vog_sim *> &sims, const std::vect
                 maxl = std::max(maxl, vsweep ? s->cfg.nx : s->cfg.nv);
             }
             EventPair *p;
-            prof_begin(lead, vsweep ? K_SWEEP_V : K_SWEEP_X, &p);
+            prof_begin(lead, vsweep ? pkind : K_SWEEP_X, &p);
             fn(b, maxl, lead->stream);
             prof_end(lead, p);
             return check_launch();
@@ -642,43 +664,57 @@ int device_guard(vog_sim *s) {
 }
 
 // nsteps Strang steps (Section 1.1) of every sim, one grouped launch per
-// kernel kind and line length.  Sims with merge_v skip the opening half
-// step of steps 1 .. nsteps-1 and advect by dt at the end of steps
-// 0 .. nsteps-2 instead (the two half steps share the field).
+// kernel kind and line length.  Between two steps of one call, the closing
+// half step of the first and the opening half step of the second share the
+// field: sims with merge_v replace them by one advection by dt (a different
+// scheme, opt-in); the others run both in one launch (sweep kind 2, the same
+// arithmetic as two launches), except where the moments need the full time
+// level in between.
 int step_sims(const std::vector<vog_sim *> &sims, const std::vector<double> &dt, int nsteps) {
     vog_sim *lead = sims[0];
     std::vector<int64_t> stepno(sims.size());
     std::vector<double> tnow(sims.size());
+    std::vector<char> opened(sims.size(), 0);  // opening half step already done
     for (int n = 0; n < nsteps; ++n) {
         const bool last = n == nsteps - 1;
-        std::vector<vog_sim *> open;  // sims that start this step with a half step
-        std::vector<double> half, tau_end(sims.size());
+        std::vector<vog_sim *> open, once, twice, msims;  // see below
+        std::vector<double> half, tau_once, tau_twice;
+        std::vector<int64_t> mstep;
         for (size_t k = 0; k < sims.size(); ++k) {
             stepno[k] = sims[k]->step + 1;
             tnow[k] = sims[k]->t + dt[k];
             const bool merge = sims[k]->cfg.merge_v != 0;
-            if (!merge || n == 0) {
+            if (!opened[k]) {  // starts this step with a half step
                 open.push_back(sims[k]);
                 half.push_back(0.5 * dt[k]);
             }
-            tau_end[k] = (merge && !last) ? dt[k] : 0.5 * dt[k];
+            // moments after this step; merged sims hold a full time level
+            // only after a call's last step
+            const int every = sims[k]->cfg.moments_every;
+            const bool due = every > 0 && stepno[k] % every == 0 && (!merge || last);
+            if (due) {
+                msims.push_back(sims[k]);
+                mstep.push_back(stepno[k]);
+            }
+            if (merge && !last) {  // closing and next opening half step as one by dt
+                once.push_back(sims[k]);
+                tau_once.push_back(dt[k]);
+            } else if (!last && !due) {  // closing and next opening half step, one launch
+                twice.push_back(sims[k]);
+                tau_twice.push_back(0.5 * dt[k]);
+            } else {
+                once.push_back(sims[k]);
+                tau_once.push_back(0.5 * dt[k]);
+            }
+            opened[k] = !last && (merge || !due);
         }
         int rc;
         if (!open.empty() && (rc = run_sweep(lead, open, half, true)) != VOG_OK) return rc;
         if ((rc = x_advection(lead, sims, dt, true)) != VOG_OK) return rc;
         if ((rc = run_field(lead, sims, stepno, tnow)) != VOG_OK) return rc;
-        if ((rc = run_sweep(lead, sims, tau_end, true)) != VOG_OK) return rc;
-        std::vector<vog_sim *> msims;
-        std::vector<int64_t> mstep;
-        for (size_t k = 0; k < sims.size(); ++k) {
-            const int every = sims[k]->cfg.moments_every;
-            // merged sims hold a full time level only after a call's last step
-            const bool level = !sims[k]->cfg.merge_v || last;
-            if (every > 0 && stepno[k] % every == 0 && level) {
-                msims.push_back(sims[k]);
-                mstep.push_back(stepno[k]);
-            }
-        }
+        if (!once.empty() && (rc = run_sweep(lead, once, tau_once, true)) != VOG_OK) return rc;
+        if (!twice.empty() && (rc = run_sweep(lead, twice, tau_twice, true, false, true)) != VOG_OK)
+            return rc;
         if (!msims.empty() && (rc = run_moments(lead, msims, mstep)) != VOG_OK) return rc;
         for (size_t k = 0; k < sims.size(); ++k) {
             sims[k]->step = stepno[k];

@@ -17,10 +17,12 @@ static LaunchFn pick_sweep(int logn, std::integer_sequence<int, L...>) {
     return fns[logn - 3];
 }
 
-LaunchFn sweep_launcher_f64(int n, bool vsweep) {
+LaunchFn sweep_launcher_f64(int n, int kind) {
     const int logn = ilog2(n);
     using Seq = std::make_integer_sequence<int, 10>;
-    return vsweep ? pick_sweep<double, 0>(logn, Seq{}) : pick_sweep<double, 1>(logn, Seq{});
+    return kind == 0   ? pick_sweep<double, 0>(logn, Seq{})
+           : kind == 1 ? pick_sweep<double, 1>(logn, Seq{})
+                       : pick_sweep<double, 2>(logn, Seq{});
 }
 
 }  // namespace vog

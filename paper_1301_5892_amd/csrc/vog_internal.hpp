@@ -66,11 +66,15 @@ struct BlockMap {
     int lgn[kMaxBatch];
 };
 
-enum Kind { K_SWEEP_V = 0, K_SWEEP_X = 1, K_T_VX = 2, K_T_XV = 3, K_FIELD = 4, K_MOMENTS = 5, K_RHO = 6 };
+enum Kind {
+    K_SWEEP_V = 0, K_SWEEP_X = 1, K_T_VX = 2, K_T_XV = 3, K_FIELD = 4, K_MOMENTS = 5, K_RHO = 6,
+    K_SWEEP_VV = 7
+};
 
 // Host-side launchers (defined in kernels.hip).
 using LaunchFn = void (*)(const Batch &, int max_lines, hipStream_t);
-LaunchFn sweep_launcher(bool fp64, int n, bool vsweep);
+// kind 0: v-sweep, 1: x-sweep on the transposed copy, 2: two v half-steps
+LaunchFn sweep_launcher(bool fp64, int n, int kind);
 // x-sweep on the v-fastest layout: lines per block (0 if not available) and launcher.
 int fused_lines_per_block(bool fp64, int nx);
 LaunchFn fused_xsweep_launcher(bool fp64, int nx);
@@ -82,7 +86,8 @@ LaunchFn field_launcher(int nx);  // nx = 2048, 4096
 // (v-sweep: lines = nx; x-sweep: lines = nv).
 int sweep_blocks_mixed(bool vsweep, int n, int lines);
 bool sweep_mixed_ok(bool vsweep, int n);
-void launch_sweep_mixed(bool vsweep, const Batch &b, const BlockMap &m, hipStream_t st);
+// kind 0: v-sweeps, 1: x-sweeps, 2: two v half-steps (blocks as for 0)
+void launch_sweep_mixed(int kind, const Batch &b, const BlockMap &m, hipStream_t st);
 // One launch of field solves over sims of 8 .. 1024 points in x, of one or
 // several lengths (block k = sim k, m.lgn[k] = log2 nx).
 bool field_mixed_ok(int nx);

@@ -23,9 +23,9 @@ INTERP_LAGRANGE, INTERP_BSPLINE = 0, 1
 POISSON_FOURIER, POISSON_TRAPEZOID = 0, 1
 FIELD_SELF_CONSISTENT, FIELD_ZERO = 0, 1
 MAX_FEQ = 4
-NUM_KINDS = 7
+NUM_KINDS = 8
 KIND_NAMES = ("sweep_v", "sweep_x", "transpose_vx", "transpose_xv_rho", "field", "moments",
-              "rho_reduce")
+              "rho_reduce", "sweep_vv")
 PRECISION = {"fp64_plain": FP64_PLAIN, "fp32_deltaf": FP32_DELTAF, "fp64_deltaf": FP64_DELTAF,
              "fp32_plain": FP32_PLAIN}
 INTERP = {"lagrange": INTERP_LAGRANGE, "bspline": INTERP_BSPLINE}
