@@ -464,13 +464,16 @@ def summarize_rocprof(folder, wname):
                 "fetch_bytes": rd, "write_bytes": wr, "bytes_per_launch": rd + wr,
                 "fetch_scale": kf, "write_scale": kw}
     if wl:
-        lines += ["", "Per Strang step (two v-sweeps, one x-sweep, the partial-row reduce and the "
-                  "field solve) against the algorithmic 3 x (read + write of f):", ""]
+        lines += ["", "Per Strang step inside a multi-step call (steady state: the two v half-steps "
+                  "between steps in one launch where there is one, else two v-sweeps; one x-sweep, "
+                  "the partial-row reduce and the field solve) against the algorithmic "
+                  "3 x (read + write of f):", ""]
         for prec, e in es.items():
             kinds = {k: v for (k, p), v in per_launch.items() if p == prec}
-            if "sweep_v" not in kinds or "sweep_x" not in kinds:
+            if "sweep_x" not in kinds or not ({"sweep_v", "sweep_vv"} & set(kinds)):
                 continue
-            per_step = {"sweep_v": 2, "sweep_x": 1, "transpose": 2, "rho_reduce": 1, "field": 1}
+            per_step = {"sweep_x": 1, "transpose": 2, "rho_reduce": 1, "field": 1}
+            per_step.update({"sweep_vv": 1} if "sweep_vv" in kinds else {"sweep_v": 2})
             step = sum(per_step.get(k, 0) * v for k, v in kinds.items())
             alg = 6 * e * wl.cells
             lines.append(f"- {prec}: {step / 1e6:.1f} MB measured, {alg / 1e6:.1f} MB algorithmic "

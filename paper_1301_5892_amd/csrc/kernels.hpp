@@ -584,7 +584,8 @@ __device__ __forceinline__ void sweep_body(const Batch &b, int sim, int blk, T *
             v[r] = cx<T>{lre[i], lim[i]};
         });
         if constexpr (kP4k) __syncthreads();  // reads done before the digit transform writes
-        transform(opaque(tw), opaque(eps), opaque(t));
+        // (the digit transform keeps t: its wave index t / 64 must stay uniform)
+        transform(opaque(tw), opaque(eps), kP4k ? t : opaque(t));
     }
 
     if (!active) return;
