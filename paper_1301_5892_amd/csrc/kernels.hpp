@@ -547,7 +547,8 @@ __device__ __forceinline__ void sweep_body(const Batch &b, int sim, int blk, T *
                 p4k_fwd_col<T>(v, tt, lre, lim, w);
             }
             __syncthreads();
-            p4k_lanes<T>(tt >> 6, tt & 63, lre, lim, LoadRows<T>{twp, eps0}, wsh[0][0], iden);
+            p4k_lanes<T>(__builtin_amdgcn_readfirstlane(tt >> 6), tt & 63, lre, lim, LoadRows<T>{twp, eps0},
+                         wsh[0][0], iden);
             __syncthreads();
             {
                 cx<T> w[16];
@@ -584,13 +585,14 @@ __device__ __forceinline__ void sweep_body(const Batch &b, int sim, int blk, T *
             v[r] = cx<T>{lre[i], lim[i]};
         });
         if constexpr (kP4k) __syncthreads();  // reads done before the digit transform writes
-        // (the digit transform keeps t: its wave index t / 64 must stay uniform)
-        transform(opaque(tw), opaque(eps), kP4k ? t : opaque(t));
+        transform(opaque(tw), opaque(eps), opaque(t));
     }
 
     if (!active) return;
 
-    store_pair<T, N, R, TPF, VS>(S, arg * EA, arg * EB, bA, bB, t, rA, oA, rB, oB, out);
+    // (KIND 2: positions formed again, not kept live from the staging above)
+    store_pair<T, N, R, TPF, VS>(S, arg * EA, arg * EB, bA, bB, KIND == 2 ? opaque(t) : t, rA, oA, rB, oB,
+                                 out);
 }
 
 // One line length per launch: blockIdx.y = sim, blockIdx.x = block.
