@@ -19,7 +19,11 @@ SOURCES = ["sweep_f32.hip", "sweep_f64.hip", "xsweep.hip", "mixed.hip", "field.h
 ARCH = os.environ.get("VOG_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-CFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+# -ffp-contract=on: a multiply and an add are fused only where one source
+# expression holds both, so a body gives the same bits whichever kernel it is
+# inlined into (the default also fuses across statements, depending on the
+# surrounding code).
+CFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=on",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
           "-I", os.path.join(HERE, "..", "include")]

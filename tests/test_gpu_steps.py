@@ -1,0 +1,95 @@
+"""Steps of one call against single-step calls, bitwise (Section 1.1).
+
+Inside one call of n steps the closing v half-step of each step and the
+opening half-step of the next use the same field, and the library runs the
+two in one launch (each line pair transformed twice, the first result staged
+through LDS).  That changes where values live between the two half-steps, not
+what is computed: f, E and every diagnostics record must be bitwise those of
+n single-step calls, for every kernel family that can take that launch
+(line lengths with several pairs per block, one wave per pair and one pair
+per block; FP32 and FP64, delta f and plain; B-splines; the KEEN drive;
+moments between steps; mixed-length batches).
+"""
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(gpu, w, split, moments_every=0, precision=None):
+    s = gpu.Sim(w, moments_every=moments_every, precision=precision).init()
+    for k in split:
+        s.step(k)
+    s.sync()
+    return s.get_raw().copy(), s.get_E().copy(), s.diag().copy()
+
+
+def _same(a, b):
+    fa, ea, da = a
+    fb, eb, db = b
+    assert np.array_equal(fa, fb)
+    assert np.array_equal(ea, eb)
+    assert da.shape == db.shape
+    assert da.tobytes() == db.tobytes()  # NaN-safe: the records' bytes
+
+
+GRIDS = [
+    ("fp32_deltaf", 64, 64),      # 8 line pairs per block, one wave per pair
+    ("fp32_deltaf", 32, 1024),    # one wave per pair
+    ("fp32_deltaf", 32, 2048),    # two pairs per block
+    ("fp32_deltaf", 32, 4096),    # one pair per block
+    ("fp32_plain", 64, 512),
+    ("fp64_plain", 64, 256),
+    ("fp64_deltaf", 32, 1024),
+    ("fp64_plain", 32, 4096),     # two launches of the one-step kernel
+]
+
+
+@pytest.mark.parametrize("precision,nx,nv", GRIDS)
+def test_call_equals_single_steps(gpu, precision, nx, nv):
+    w = workloads.landau_strong().replace(nx=nx, nv=nv, precision=precision)
+    _same(_run(gpu, w, [6]), _run(gpu, w, [1] * 6))
+
+
+def test_call_chunks_equal(gpu):
+    w = workloads.bump_on_tail().replace(nx=256, nv=512)
+    ref = _run(gpu, w, [9])
+    _same(ref, _run(gpu, w, [4, 5]))
+    _same(ref, _run(gpu, w, [2, 1, 6]))
+
+
+def test_moments_between_steps(gpu):
+    # moments due after steps 2 and 4: those steps close with a single half step
+    w = workloads.landau_strong().replace(nx=64, nv=256)
+    a = _run(gpu, w, [5], moments_every=2)
+    b = _run(gpu, w, [1] * 5, moments_every=2)
+    _same(a, b)
+    d = a[2]
+    due = (d["step"] > 0) & (d["step"] % 2 == 0)
+    assert due.sum() == 2 and np.isfinite(d["l2"][due]).all()
+
+
+def test_bspline(gpu):
+    w = workloads.landau_strong().replace(nx=64, nv=512, interp="bspline", degree=5)
+    _same(_run(gpu, w, [5]), _run(gpu, w, [1] * 5))
+
+
+def test_keen_drive(gpu):
+    # the drive on from t = 0: the advecting field E - E_app differs from E
+    d = workloads.Drive(t0=-60.0, tl=-50.0)
+    w = workloads.keen(128, 0.1, 10).replace(drive=d)
+    _same(_run(gpu, w, [6]), _run(gpu, w, [1] * 6))
+
+
+def test_mixed_batch_call_equals_single_steps(gpu):
+    from paper_1301_5892_amd import vog
+    ws = [workloads.landau_strong().replace(nx=64, nv=n) for n in (128, 1024, 4096)]
+    ws.append(workloads.landau_weak().replace(nx=128, nv=256))
+    alone = [_run(gpu, w, [1] * 4) for w in ws]
+    sims = [gpu.Sim(w).init() for w in ws]
+    vog.step_batch(sims, 4)
+    for s, a in zip(sims, alone):
+        s.sync()
+        _same((s.get_raw(), s.get_E(), s.diag()), a)
