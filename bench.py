@@ -582,6 +582,11 @@ def main():
                              "kernels_ms_per_step": {k: v[0] / K for k, v in prof64.items()},
                              "roofline": roofline_for(w, "fp64_plain", prof64, K)}
         out["fp32_over_fp64"] = out["value"] / out["fp64_plain"]["value"]
+        # FP64 delta f (optional in the comparison): the same grid, f - f_eq
+        # stored in FP64
+        el64d, _, fin64d, _ = run_gpu(w, "fp64_deltaf", K, W)
+        out["fp64_deltaf"] = {"value": w.cells * K / el64d, "ms_per_step": el64d / K * 1e3,
+                              "finite": fin64d}
     if not args.no_keen:
         # The paper's timed workload (Section 4.3, Table 1): KEEN waves at
         # N = 4096, FP32 delta f, drive on; its C2070 figure is quoted as is.

@@ -191,8 +191,11 @@ int vog_set_E(vog_sim *sim, const double *host_E);
  * configuration sets merge_v.  Each constant advection is the circulant
  * product A u of Section 1.2 (Lagrange 2d+1 or B-spline coefficients),
  * applied as FFT -> multiply by the diagonal of A in Fourier space ->
- * inverse FFT.  With a drive, the v-advections use E - E_app.  Asynchronous:
- * returns after enqueueing.  dt > 0 and finite, nsteps >= 0 (0: no-op). */
+ * inverse FFT.  With a drive, the v-advections use E - E_app.  Between two
+ * steps of one call the closing half step and the next opening one may run
+ * in one launch; f, E and the diagnostics records are bitwise those of
+ * nsteps calls of one step.  Asynchronous: returns after enqueueing.
+ * dt > 0 and finite, nsteps >= 0 (0: no-op). */
 int vog_step(vog_sim *sim, double dt, int nsteps);
 
 /* nsteps Strang steps (Section 1.1, the time loop of Section 2) for nsims
