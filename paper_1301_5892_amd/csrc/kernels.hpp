@@ -448,7 +448,7 @@ struct Sweep {
 
 // Block blk of sim `sim` of the batch; smem holds Sweep<T, N>::SMEM values.
 template <typename T, int N, int KIND>
-__device__ __forceinline__ void sweep_body(const Batch &b, int sim, int blk, T *smem) {
+__device__ __forceinline__ void sweep_body(const SweepBatch &b, int sim, int blk, T *smem) {
     using F = Fft<T, N>;
     constexpr int R = F::R, TPF = F::TPF, PPB = Sweep<T, N>::PPB;
     T(*lds)[2][F::LDSN] = reinterpret_cast<T(*)[2][F::LDSN]>(smem);
@@ -597,20 +597,21 @@ __device__ __forceinline__ void sweep_body(const Batch &b, int sim, int blk, T *
 
 // One line length per launch: blockIdx.y = sim, blockIdx.x = block.
 template <typename T, int N, int KIND>
-__global__ __launch_bounds__(256, (sizeof(T) == 4 && N >= 32 ? 3 : 1)) void sweep_kernel(const Batch b) {
+__global__ __launch_bounds__(256, (sizeof(T) == 4 && N >= 32 ? 3 : 1)) void sweep_kernel(const SweepBatch b) {
     __shared__ T smem[Sweep<T, N>::SMEM];
     sweep_body<T, N, KIND>(b, (int)blockIdx.y, (int)blockIdx.x, smem);
 }
 
 // Sim of block bid in a launch over mixed line lengths (m.first ascending,
-// m.first[0] = 0): the number of j in 1 .. n-1 with first[j] <= bid, one
-// candidate j per lane of the wave, counted with a ballot.  All 64 lanes of
-// the wave must call it.
-static_assert(kMaxBatch <= 64, "one lane per candidate sim");
-__device__ __forceinline__ int mixed_sim(const Batch &b, const BlockMap &m, int bid) {
-    const int j = (int)(threadIdx.x & 63) + 1;
+// m.first[0] = 0): the number of j in 1 .. n-1 with first[j] <= bid, two
+// candidates j per lane of the wave, counted with two ballots.  All 64 lanes
+// of the wave must call it.
+static_assert(kMaxSweepBatch <= 128, "two candidate sims per lane");
+__device__ __forceinline__ int mixed_sim(const SweepBatch &b, const SweepMap &m, int bid) {
+    const int j = (int)(threadIdx.x & 63) + 1, j2 = j + 64;
     const bool le = j < b.n && m.first[j] <= bid;
-    return __builtin_amdgcn_readfirstlane(__popcll(__ballot(le)));
+    const bool le2 = j2 < b.n && m.first[j2] <= bid;
+    return __builtin_amdgcn_readfirstlane(__popcll(__ballot(le)) + __popcll(__ballot(le2)));
 }
 
 // x-advection by dt = b.a[sim] directly on the v-fastest layout f[nx][nv]
@@ -649,7 +650,7 @@ constexpr int kFusedThreads = Fused<T, N>::TB;
 
 // Block hb of sim `sim`; smem holds Fused<T, N>::SMEM values.
 template <typename T, int N>
-__device__ __forceinline__ void xsweep_body(const Batch &b, int sim, int hb, T *smem) {
+__device__ __forceinline__ void xsweep_body(const SweepBatch &b, int sim, int hb, T *smem) {
     using F = Fft<T, N>;
     using C = Fused<T, N>;
     constexpr int R = F::R, TPF = F::TPF;
@@ -747,7 +748,7 @@ __device__ __forceinline__ void xsweep_body(const Batch &b, int sim, int hb, T *
 }
 
 template <typename T, int N>
-__global__ __launch_bounds__((kFusedThreads<T, N>), (Fused<T, N>::WAVES)) void xsweep_fused_kernel(const Batch b) {
+__global__ __launch_bounds__((kFusedThreads<T, N>), (Fused<T, N>::WAVES)) void xsweep_fused_kernel(const SweepBatch b) {
     __shared__ T smem[Fused<T, N>::SMEM];
     xsweep_body<T, N>(b, (int)blockIdx.y, (int)blockIdx.x, smem);
 }

@@ -6,10 +6,10 @@
 
 namespace vog {
 
-LaunchFn sweep_launcher_f32(int n, int kind);
-LaunchFn sweep_launcher_f64(int n, int kind);
+SweepFn sweep_launcher_f32(int n, int kind);
+SweepFn sweep_launcher_f64(int n, int kind);
 
-LaunchFn sweep_launcher(bool fp64, int n, int kind) {
+SweepFn sweep_launcher(bool fp64, int n, int kind) {
     const int logn = ilog2(n);
     if (n < VOG_MIN_N || n > VOG_MAX_N || (1 << logn) != n || kind < 0 || kind > 2) return nullptr;
     return fp64 ? sweep_launcher_f64(n, kind) : sweep_launcher_f32(n, kind);
@@ -62,14 +62,14 @@ __global__ __launch_bounds__(256) void transpose_kernel(const Batch b) {
 }
 
 // rho from the partial velocity sums, one block per 16 x-columns.
-__global__ __launch_bounds__(256) void rho_reduce_kernel(const Batch b) {
+__global__ __launch_bounds__(256) void rho_reduce_kernel(const SweepBatch b) {
     __shared__ double red[256];
     const SimDev &S = *b.s[blockIdx.y];
     if ((int)blockIdx.x * kRhoCols >= S.nx) return;  // whole block
     rho_columns<256 / kRhoCols, 16>(S, (int)blockIdx.x * kRhoCols, red);
 }
 
-void launch_rho_reduce(const Batch &b, int max_nx, hipStream_t st) {
+void launch_rho_reduce(const SweepBatch &b, int max_nx, hipStream_t st) {
     hipLaunchKernelGGL(rho_reduce_kernel, dim3((max_nx + kRhoCols - 1) / kRhoCols, b.n), dim3(256), 0, st, b);
 }
 

@@ -9,7 +9,7 @@ namespace vog {
 // values whatever the length).
 // KIND 0: one v half-step; KIND 2: two in a row (sweep_body).
 template <int KIND>
-__global__ __launch_bounds__(256, 3) void sweep_v_mixed_kernel(const Batch b, const BlockMap m) {
+__global__ __launch_bounds__(256, 3) void sweep_v_mixed_kernel(const SweepBatch b, const SweepMap m) {
     __shared__ float smem[Sweep<float, 64>::SMEM];  // the largest of 64 .. 4096
     const int bid = (int)blockIdx.x;
     const int k = mixed_sim(b, m, bid);
@@ -29,7 +29,7 @@ __global__ __launch_bounds__(256, 3) void sweep_v_mixed_kernel(const Batch b, co
 // FP32 x-sweeps of sims with x-lines of 64 .. 1024 points in one launch
 // (256-thread blocks for all of them).  Each sim's first block is a multiple
 // of 8, so the XCD-aware tile order holds.
-__global__ __launch_bounds__(256, 3) void xsweep_mixed_kernel(const Batch b, const BlockMap m) {
+__global__ __launch_bounds__(256, 3) void xsweep_mixed_kernel(const SweepBatch b, const SweepMap m) {
     __shared__ float smem[Fused<float, 64>::SMEM];  // the largest of 64 .. 1024
     const int bid = (int)blockIdx.x;
     const int k = mixed_sim(b, m, bid);
@@ -75,7 +75,7 @@ int sweep_blocks_mixed(bool vsweep, int n, int lines) {
     return (tiles + 7) / 8 * 8;
 }
 
-void launch_sweep_mixed(int kind, const Batch &b, const BlockMap &m, hipStream_t st) {
+void launch_sweep_mixed(int kind, const SweepBatch &b, const SweepMap &m, hipStream_t st) {
     const int blocks = m.first[b.n];
     if (kind == 0) hipLaunchKernelGGL(sweep_v_mixed_kernel<0>, dim3(blocks), dim3(256), 0, st, b, m);
     else if (kind == 2) hipLaunchKernelGGL(sweep_v_mixed_kernel<2>, dim3(blocks), dim3(256), 0, st, b, m);

@@ -384,11 +384,13 @@ struct Group {
     std::vector<double> arg;
 };
 
-template <typename Fn>
+// Chunks of up to B's capacity (Batch: kMaxBatch, SweepBatch: kMaxSweepBatch).
+template <typename B = Batch, typename Fn>
 int for_chunks(const Group &g, Fn &&fn) {
-    for (size_t base = 0; base < g.sims.size(); base += kMaxBatch) {
-        Batch b{};
-        b.n = (int)std::min<size_t>(kMaxBatch, g.sims.size() - base);
+    constexpr size_t cap = sizeof(B::s) / sizeof(B::s[0]);
+    for (size_t base = 0; base < g.sims.size(); base += cap) {
+        B b{};
+        b.n = (int)std::min<size_t>(cap, g.sims.size() - base);
         for (int k = 0; k < b.n; ++k) {
             b.s[k] = g.sims[base + k]->dev;
             b.a[k] = g.arg.empty() ? 0.0 : g.arg[base + k];
@@ -464,8 +466,8 @@ int run_sweep(vog_sim *lead, const std::vector<vog_sim *> &sims, const std::vect
         }
     }
     if (!mixed.sims.empty()) {
-        int rc = for_chunks(mixed, [&](const Batch &b, size_t base) {
-            BlockMap m{};
+        int rc = for_chunks<SweepBatch>(mixed, [&](const SweepBatch &b, size_t base) {
+            SweepMap m{};
             for (int k = 0; k < b.n; ++k) {
                 const vog_sim *s = mixed.sims[base + k];
                 const int n = vsweep ? s->cfg.nv : s->cfg.nx;
@@ -483,11 +485,11 @@ int run_sweep(vog_sim *lead, const std::vector<vog_sim *> &sims, const std::vect
     for (auto &kv : groups) {
         const bool fp64 = (kv.first.first & 1) != 0;
         const int xmode = kv.first.first / 2;
-        LaunchFn fn = vsweep             ? sweep_launcher(fp64, kv.first.second, vkind)
+        SweepFn fn = vsweep              ? sweep_launcher(fp64, kv.first.second, vkind)
                       : xmode == X_TILED ? fused_xsweep_launcher(fp64, kv.first.second)
                                          : sweep_launcher(fp64, kv.first.second, 1);
         if (!fn) return fail(VOG_EINVAL, "no sweep kernel for this line length");
-        int rc = for_chunks(kv.second, [&](const Batch &b, size_t base) {
+        int rc = for_chunks<SweepBatch>(kv.second, [&](const SweepBatch &b, size_t base) {
             int maxl = 0;
             for (int k = 0; k < b.n; ++k) {
                 const vog_sim *s = kv.second.sims[base + k];
@@ -532,7 +534,7 @@ int run_transpose(vog_sim *lead, const std::vector<vog_sim *> &sims, bool to_v) 
 int run_rho_reduce(vog_sim *lead, const std::vector<vog_sim *> &sims) {
     Group g;
     g.sims = sims;
-    return for_chunks(g, [&](const Batch &b, size_t base) {
+    return for_chunks<SweepBatch>(g, [&](const SweepBatch &b, size_t base) {
         int maxnx = 0;
         for (int k = 0; k < b.n; ++k) maxnx = std::max(maxnx, g.sims[base + k]->cfg.nx);
         EventPair *p;

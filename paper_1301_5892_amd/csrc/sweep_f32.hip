@@ -5,19 +5,19 @@
 namespace vog {
 
 template <typename T, int N, int KIND>
-static void launch_sweep(const Batch &b, int max_lines, hipStream_t st) {
+static void launch_sweep(const SweepBatch &b, int max_lines, hipStream_t st) {
     constexpr int PPB = 256 / Fft<T, N>::TPF;
     const int blocks = (max_lines / 2 + PPB - 1) / PPB;
     hipLaunchKernelGGL((sweep_kernel<T, N, KIND>), dim3(blocks, b.n), dim3(256), 0, st, b);
 }
 
 template <typename T, int KIND, int... L>
-static LaunchFn pick_sweep(int logn, std::integer_sequence<int, L...>) {
-    LaunchFn fns[] = {&launch_sweep<T, (8 << L), KIND>...};
+static SweepFn pick_sweep(int logn, std::integer_sequence<int, L...>) {
+    SweepFn fns[] = {&launch_sweep<T, (8 << L), KIND>...};
     return fns[logn - 3];
 }
 
-LaunchFn sweep_launcher_f32(int n, int kind) {
+SweepFn sweep_launcher_f32(int n, int kind) {
     const int logn = ilog2(n);
     using Seq = std::make_integer_sequence<int, 10>;
     return kind == 0   ? pick_sweep<float, 0>(logn, Seq{})

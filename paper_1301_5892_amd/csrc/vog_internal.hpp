@@ -10,7 +10,8 @@ namespace vog {
 
 constexpr int kDMax = 8;                 // Lagrange 2d+1 with d <= 8
 constexpr int kTaps = 2 * kDMax + 2;     // 18 stencil offsets q = -8 .. 9
-constexpr int kMaxBatch = 64;            // sims per grouped launch
+constexpr int kMaxBatch = 64;            // sims per grouped launch (field solve, reductions)
+constexpr int kMaxSweepBatch = 128;      // sims per grouped sweep launch
 constexpr int kRingCap = 4096;           // diagnostics records kept per sim
 constexpr int kTile = 64;                // transpose tile edge
 constexpr int kRhoCols = 16;             // x-columns per block of the partial-row reduction
@@ -58,13 +59,26 @@ struct Batch {
     double drv_ph[kMaxBatch];   // omega t (field solve)
 };
 
-// Blocks of one launch over FP32 sims whose lines have different lengths:
-// sim k owns the blocks first[k] .. first[k+1] - 1 and its lines have
-// 2^lgn[k] points.
-struct BlockMap {
-    int first[kMaxBatch + 1];
-    int lgn[kMaxBatch];
+// Kernel argument of a grouped sweep launch: up to kMaxSweepBatch sims, each
+// with its tau (v-sweep) or dt (x-sweep).  Smaller than Batch, so that one
+// launch covers twice as many sims within the 4 KB of kernel arguments.
+struct SweepBatch {
+    int n;
+    int pad_;
+    const SimDev *s[kMaxSweepBatch];
+    double a[kMaxSweepBatch];
 };
+
+// Blocks of one launch over sims whose lines have different lengths: sim k
+// owns the blocks first[k] .. first[k+1] - 1 and its lines have 2^lgn[k]
+// points.
+template <int CAP>
+struct BlockMapT {
+    int first[CAP + 1];
+    int lgn[CAP];
+};
+using BlockMap = BlockMapT<kMaxBatch>;        // field solves
+using SweepMap = BlockMapT<kMaxSweepBatch>;   // sweeps
 
 enum Kind {
     K_SWEEP_V = 0, K_SWEEP_X = 1, K_T_VX = 2, K_T_XV = 3, K_FIELD = 4, K_MOMENTS = 5, K_RHO = 6,
@@ -73,11 +87,12 @@ enum Kind {
 
 // Host-side launchers (defined in kernels.hip).
 using LaunchFn = void (*)(const Batch &, int max_lines, hipStream_t);
+using SweepFn = void (*)(const SweepBatch &, int max_lines, hipStream_t);
 // kind 0: v-sweep, 1: x-sweep on the transposed copy, 2: two v half-steps
-LaunchFn sweep_launcher(bool fp64, int n, int kind);
+SweepFn sweep_launcher(bool fp64, int n, int kind);
 // x-sweep on the v-fastest layout: lines per block (0 if not available) and launcher.
 int fused_lines_per_block(bool fp64, int nx);
-LaunchFn fused_xsweep_launcher(bool fp64, int nx);
+SweepFn fused_xsweep_launcher(bool fp64, int nx);
 void launch_transpose(bool fp64, bool to_v, const Batch &b, int max_tiles, hipStream_t st);
 LaunchFn field_launcher(int nx);  // nx = 2048, 4096
 // One launch of FP32 v-sweeps (lines of 64 .. 4096 points) or FP32 x-sweeps on
@@ -87,13 +102,13 @@ LaunchFn field_launcher(int nx);  // nx = 2048, 4096
 int sweep_blocks_mixed(bool vsweep, int n, int lines);
 bool sweep_mixed_ok(bool vsweep, int n);
 // kind 0: v-sweeps, 1: x-sweeps, 2: two v half-steps (blocks as for 0)
-void launch_sweep_mixed(int kind, const Batch &b, const BlockMap &m, hipStream_t st);
+void launch_sweep_mixed(int kind, const SweepBatch &b, const SweepMap &m, hipStream_t st);
 // One launch of field solves over sims of 8 .. 1024 points in x, of one or
 // several lengths (block k = sim k, m.lgn[k] = log2 nx).
 bool field_mixed_ok(int nx);
 void launch_field_mixed(const Batch &b, const BlockMap &m, hipStream_t st);
 void launch_rho_v(bool fp64, const Batch &b, int max_nx, hipStream_t st);
-void launch_rho_reduce(const Batch &b, int max_nx, hipStream_t st);
+void launch_rho_reduce(const SweepBatch &b, int max_nx, hipStream_t st);
 void launch_moments(bool fp64, const Batch &b, int max_nx, hipStream_t st);
 void launch_init(bool fp64, const SimDev *s, int cells, int nmodes, const double *amp,
                  const double *kx, const double *ph, hipStream_t st);

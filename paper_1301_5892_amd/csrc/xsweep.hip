@@ -5,15 +5,15 @@
 namespace vog {
 
 template <typename T, int N>
-static void launch_xsweep_fused(const Batch &b, int max_lines, hipStream_t st) {
+static void launch_xsweep_fused(const SweepBatch &b, int max_lines, hipStream_t st) {
     using C = Fused<T, N>;
     const int blocks = max_lines / C::B;
     hipLaunchKernelGGL((xsweep_fused_kernel<T, N>), dim3(blocks, b.n), dim3(C::TB), 0, st, b);
 }
 
 template <typename T, int... L>
-static LaunchFn pick_fused(int logn, std::integer_sequence<int, L...>) {
-    LaunchFn fns[] = {&launch_xsweep_fused<T, (64 << L)>...};
+static SweepFn pick_fused(int logn, std::integer_sequence<int, L...>) {
+    SweepFn fns[] = {&launch_xsweep_fused<T, (64 << L)>...};
     return fns[logn - 6];
 }
 
@@ -31,7 +31,7 @@ int fused_lines_per_block(bool fp64, int nx) {
     return fp64 ? td[logn - 6] : tf[logn - 6];
 }
 
-LaunchFn fused_xsweep_launcher(bool fp64, int nx) {
+SweepFn fused_xsweep_launcher(bool fp64, int nx) {
     if (fused_lines_per_block(fp64, nx) == 0) return nullptr;
     using Seq = std::make_integer_sequence<int, 7>;
     return fp64 ? pick_fused<double>(ilog2(nx), Seq{}) : pick_fused<float>(ilog2(nx), Seq{});
