@@ -235,10 +235,14 @@ __device__ __forceinline__ void deltaf_source(const SimDev &S, double tauE, int 
 // (imaginary part).  Unshifted index j goes to line position (j - b) mod N;
 // sinkA(pos, x) and sinkB(pos, x) receive each value x with the byte offset
 // pos of its position in the line.  VSWEEP: adds the delta-f source
-// (Section 3.1) with tau E of each line.
-template <typename T, int N, int R, int TPF, bool VSWEEP, typename Out, typename SinkA, typename SinkB>
+// (Section 3.1) with tau E of each line.  CACHE 1: also keeps line A's source
+// values in srcA[k TPF + t]; CACHE 2: takes them from there instead of
+// computing them (the same positions, tau and E).
+template <typename T, int N, int R, int TPF, bool VSWEEP, int CACHE = 0, typename Out, typename SinkA,
+          typename SinkB>
 __device__ __forceinline__ void emit_pair(const SimDev &S, double tauEA, double tauEB, long long bA,
-                                          long long bB, int t, Out &&out, SinkA &&sinkA, SinkB &&sinkB) {
+                                          long long bB, int t, Out &&out, SinkA &&sinkA, SinkB &&sinkB,
+                                          T *srcA = nullptr) {
     constexpr unsigned LB = N * sizeof(T);  // bytes per line
     const int p0A = (t - (int)(bA & (N - 1))) & (N - 1);
     const int p0B = (t - (int)(bB & (N - 1))) & (N - 1);
@@ -254,7 +258,13 @@ __device__ __forceinline__ void emit_pair(const SimDev &S, double tauEA, double 
         if (S.deltaf) {
             T src[R];
             positions(p0A, pos);
-            deltaf_source<T, N, R, TPF>(S, tauEA, p0A, pos, src);
+            if constexpr (CACHE == 2) {
+                static_for<0, R>([&](auto kc) { src[decltype(kc)::value] = srcA[decltype(kc)::value * TPF + t]; });
+            } else {
+                deltaf_source<T, N, R, TPF>(S, tauEA, p0A, pos, src);
+                if constexpr (CACHE == 1)
+                    static_for<0, R>([&](auto kc) { srcA[decltype(kc)::value * TPF + t] = src[decltype(kc)::value]; });
+            }
             static_for<0, R>([&](auto kc) {
                 constexpr int k = decltype(kc)::value;
                 sinkA(pos[k], out(kc).re + src[k]);
@@ -281,13 +291,14 @@ __device__ __forceinline__ void emit_pair(const SimDev &S, double tauEA, double 
 }
 
 // emit_pair into f: lines A and B through their descriptors and offsets.
-template <typename T, int N, int R, int TPF, bool VSWEEP, typename Out>
+template <typename T, int N, int R, int TPF, bool VSWEEP, int CACHE = 0, typename Out>
 __device__ __forceinline__ void store_pair(const SimDev &S, double tauEA, double tauEB, long long bA,
                                            long long bB, int t, __amdgpu_buffer_rsrc_t rA, unsigned oA,
-                                           __amdgpu_buffer_rsrc_t rB, unsigned oB, Out &&out) {
-    emit_pair<T, N, R, TPF, VSWEEP>(
+                                           __amdgpu_buffer_rsrc_t rB, unsigned oB, Out &&out,
+                                           T *srcA = nullptr) {
+    emit_pair<T, N, R, TPF, VSWEEP, CACHE>(
         S, tauEA, tauEB, bA, bB, t, out, [&](unsigned pos, T x) { buf_store<T>(x, rA, oA + pos, 0); },
-        [&](unsigned pos, T x) { buf_store<T>(x, rB, oB + pos, 0); });
+        [&](unsigned pos, T x) { buf_store<T>(x, rB, oB + pos, 0); }, srcA);
 }
 
 // Weights of a line pair for its fractional shifts sA, sB, combined for the
@@ -444,10 +455,18 @@ struct Sweep {
     static constexpr int PPB = 256 / F::TPF;  // line pairs per 256-thread block
     // LDS: the pairs' exchange arrays, then their weights
     static constexpr int SMEM = PPB * 2 * F::LDSN + PPB * 2 * kTaps;
+    // KIND 2 in FP32 also keeps line A's delta-f source values of each pair
+    // between its two half steps (PPB N = 4096 values, 16 KB) where 3 blocks
+    // per CU still fit the 160 KB of LDS (lines of 256 points or more)
+    static constexpr bool SRC_CACHE = sizeof(T) == 4 && 3 * (SMEM + PPB * N) * (int)sizeof(T) <= 160 * 1024;
+    static constexpr int SMEM2 = SMEM + (SRC_CACHE ? PPB * N : 0);
 };
 
-// Block blk of sim `sim` of the batch; smem holds Sweep<T, N>::SMEM values.
-template <typename T, int N, int KIND>
+// Block blk of sim `sim` of the batch; smem holds Sweep<T, N>::SMEM values
+// (KIND 2: SMEM2).
+// CACHE_SRC: KIND 2 may keep line A's source values in smem past SMEM (the
+// mixed-length kernel, whose LDS is sized for its shortest lines, does not).
+template <typename T, int N, int KIND, bool CACHE_SRC = Sweep<T, N>::SRC_CACHE>
 __device__ __forceinline__ void sweep_body(const SweepBatch &b, int sim, int blk, T *smem) {
     using F = Fft<T, N>;
     constexpr int R = F::R, TPF = F::TPF, PPB = Sweep<T, N>::PPB;
@@ -468,6 +487,7 @@ __device__ __forceinline__ void sweep_body(const SweepBatch &b, int sim, int blk
     const int lineB = lineA + 1;
     T *lre = lds[slot][0];
     T *lim = lds[slot][1];
+    T *srcA = smem + Sweep<T, N>::SMEM + slot * N;  // KIND 2 FP32: line A's source values
     const cx<T> *tw = (const cx<T> *)(VS ? S.tw_v : S.tw_x);
     const cx<T> *eps = (const cx<T> *)(VS ? S.eps_v : S.eps_x) + t * kEpsRow;
     // One pair per block: a descriptor per line (uniform base).  Otherwise one
@@ -574,10 +594,10 @@ __device__ __forceinline__ void sweep_body(const SweepBatch &b, int sim, int blk
         // The pair's threads are one wave for lines of at most 1024 points.
         constexpr bool WAVE = !kP4k && TPF <= 64;
         xsync<WAVE>();
-        emit_pair<T, N, R, TPF, true>(
+        emit_pair<T, N, R, TPF, true, (CACHE_SRC ? 1 : 0)>(
             S, arg * EA, arg * EB, bA, bB, t, out,
             [&](unsigned pos, T x) { lre[F::pad((int)(pos / sizeof(T)))] = x; },
-            [&](unsigned pos, T x) { lim[F::pad((int)(pos / sizeof(T)))] = x; });
+            [&](unsigned pos, T x) { lim[F::pad((int)(pos / sizeof(T)))] = x; }, srcA);
         xsync<WAVE>();
         static_for<0, R>([&](auto rc) {
             constexpr int r = decltype(rc)::value;
@@ -590,15 +610,17 @@ __device__ __forceinline__ void sweep_body(const SweepBatch &b, int sim, int blk
 
     if (!active) return;
 
-    // (KIND 2: positions formed again, not kept live from the staging above)
-    store_pair<T, N, R, TPF, VS>(S, arg * EA, arg * EB, bA, bB, KIND == 2 ? opaque(t) : t, rA, oA, rB, oB,
-                                 out);
+    // (KIND 2: positions formed again, not kept live from the staging above;
+    // line A's source values from the staging's cache)
+    constexpr int CACHE = (KIND == 2 && CACHE_SRC) ? 2 : 0;
+    store_pair<T, N, R, TPF, VS, CACHE>(S, arg * EA, arg * EB, bA, bB, KIND == 2 ? opaque(t) : t, rA, oA, rB,
+                                        oB, out, srcA);
 }
 
 // One line length per launch: blockIdx.y = sim, blockIdx.x = block.
 template <typename T, int N, int KIND>
 __global__ __launch_bounds__(256, (sizeof(T) == 4 && N >= 32 ? 3 : 1)) void sweep_kernel(const SweepBatch b) {
-    __shared__ T smem[Sweep<T, N>::SMEM];
+    __shared__ T smem[KIND == 2 ? Sweep<T, N>::SMEM2 : Sweep<T, N>::SMEM];
     sweep_body<T, N, KIND>(b, (int)blockIdx.y, (int)blockIdx.x, smem);
 }
 

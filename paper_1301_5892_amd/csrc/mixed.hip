@@ -15,13 +15,13 @@ __global__ __launch_bounds__(256, 3) void sweep_v_mixed_kernel(const SweepBatch 
     const int k = mixed_sim(b, m, bid);
     const int blk = bid - m.first[k];
     switch (m.lgn[k]) {
-    case 6: sweep_body<float, 64, KIND>(b, k, blk, smem); break;
-    case 7: sweep_body<float, 128, KIND>(b, k, blk, smem); break;
-    case 8: sweep_body<float, 256, KIND>(b, k, blk, smem); break;
-    case 9: sweep_body<float, 512, KIND>(b, k, blk, smem); break;
-    case 10: sweep_body<float, 1024, KIND>(b, k, blk, smem); break;
-    case 11: sweep_body<float, 2048, KIND>(b, k, blk, smem); break;
-    case 12: sweep_body<float, 4096, KIND>(b, k, blk, smem); break;
+    case 6: sweep_body<float, 64, KIND, false>(b, k, blk, smem); break;
+    case 7: sweep_body<float, 128, KIND, false>(b, k, blk, smem); break;
+    case 8: sweep_body<float, 256, KIND, false>(b, k, blk, smem); break;
+    case 9: sweep_body<float, 512, KIND, false>(b, k, blk, smem); break;
+    case 10: sweep_body<float, 1024, KIND, false>(b, k, blk, smem); break;
+    case 11: sweep_body<float, 2048, KIND, false>(b, k, blk, smem); break;
+    case 12: sweep_body<float, 4096, KIND, false>(b, k, blk, smem); break;
     default: break;
     }
 }
