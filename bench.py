@@ -45,6 +45,9 @@ def parse():
     p.add_argument("--warmup", type=int, default=20)
     p.add_argument("--workload", default="large_grid")
     p.add_argument("--no-fp64", action="store_true")
+    p.add_argument("--no-fp64-deltaf", action="store_true",
+                   help="skip the FP64 delta-f leg (it shares kernels with FP64 plain, so the "
+                        "profiling runs leave it out)")
     p.add_argument("--no-keen", action="store_true",
                    help="skip the KEEN 4096x4096 leg (the paper's timed workload)")
     p.add_argument("--no-merged", action="store_true",
@@ -273,14 +276,14 @@ def cpu_baseline(w, seconds):
 # that scales FETCH_SIZE and WRITE_SIZE to bytes.
 PROFILE_COMMANDS = {
     "kt": "rocprofv3 --kernel-trace --stats -f csv -d {out}/kt -o kt -- python3 {root}/bench.py "
-          "--steps 100 --warmup 10 --no-serving --no-cpu-baseline --dram-sims 0 --no-merged --no-keen > {out}/kt.log",
+          "--steps 100 --warmup 10 --no-serving --no-cpu-baseline --dram-sims 0 --no-merged --no-keen --no-fp64-deltaf > {out}/kt.log",
     "fetch": "rocprofv3 --pmc FETCH_SIZE -f csv -d {out}/fetch -o fetch -- python3 {root}/bench.py "
-             "--steps 2 --warmup 1 --no-serving --no-cpu-baseline --dram-sims 0 --no-merged --no-keen --copy-calibration",
+             "--steps 2 --warmup 1 --no-serving --no-cpu-baseline --dram-sims 0 --no-merged --no-keen --no-fp64-deltaf --copy-calibration",
     "write": "rocprofv3 --pmc WRITE_SIZE -f csv -d {out}/write -o write -- python3 {root}/bench.py "
-             "--steps 2 --warmup 1 --no-serving --no-cpu-baseline --dram-sims 0 --no-merged --no-keen --copy-calibration",
+             "--steps 2 --warmup 1 --no-serving --no-cpu-baseline --dram-sims 0 --no-merged --no-keen --no-fp64-deltaf --copy-calibration",
     "valu": "rocprofv3 --pmc SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_BUSY_CU_CYCLES SQ_WAVE_CYCLES "
             "SQ_INSTS_LDS SQ_WAIT_INST_LDS -f csv -d {out}/valu -o valu -- python3 {root}/bench.py "
-            "--steps 2 --warmup 1 --no-serving --no-cpu-baseline --dram-sims 0 --no-merged --no-keen --copy-calibration",
+            "--steps 2 --warmup 1 --no-serving --no-cpu-baseline --dram-sims 0 --no-merged --no-keen --no-fp64-deltaf --copy-calibration",
 }
 COPY_CALIBRATION_BYTES = 256 << 20
 
@@ -582,6 +585,7 @@ def main():
                              "kernels_ms_per_step": {k: v[0] / K for k, v in prof64.items()},
                              "roofline": roofline_for(w, "fp64_plain", prof64, K)}
         out["fp32_over_fp64"] = out["value"] / out["fp64_plain"]["value"]
+    if not args.no_fp64 and not args.no_fp64_deltaf:
         # FP64 delta f (optional in the comparison): the same grid, f - f_eq
         # stored in FP64
         el64d, _, fin64d, _ = run_gpu(w, "fp64_deltaf", K, W)
