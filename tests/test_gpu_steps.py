@@ -93,3 +93,23 @@ def test_mixed_batch_call_equals_single_steps(gpu):
     for s, a in zip(sims, alone):
         s.sync()
         _same((s.get_raw(), s.get_E(), s.diag()), a)
+
+
+def test_batch_of_130_mixed_lengths(gpu):
+    # More sims than one launch of 64, and than one sweep launch of 128: the
+    # sweeps' launch table (two ballots per wave) and the chunking at 128,
+    # the field solves' chunking at 64.
+    from paper_1301_5892_amd import vog
+    rng = np.random.default_rng(5)
+    ws = []
+    for k in range(130):
+        nx = int(2 ** rng.integers(5, 8))     # 32 .. 128
+        nv = int(2 ** rng.integers(6, 10))    # 64 .. 512
+        ws.append(workloads.landau_strong().replace(nx=nx, nv=nv, amp=(0.05 + 0.003 * k,)))
+    sims = [gpu.Sim(w).init() for w in ws]
+    vog.step_batch(sims, 3)
+    for s in sims:
+        s.sync()
+    for k in (0, 63, 64, 65, 100, 127, 128, 129):
+        a = _run(gpu, ws[k], [3])
+        _same((sims[k].get_raw(), sims[k].get_E(), sims[k].diag()), a)
