@@ -300,7 +300,7 @@ def classify_kernel(name):
         return ("sweep_x", prec)
     if "sweep_kernel" in name:
         tail = name.split("(")[0].rstrip()
-        return ({", 1>": "sweep_x", ", 2>": "sweep_vv"}.get(tail[-4:], "sweep_v"), prec)
+        return ({", 1>": "sweep_x", ", 2>": "sweep_vv", ", 3>": "sweep_vv"}.get(tail[-4:], "sweep_v"), prec)
     if "transpose_kernel" in name:
         return ("transpose", prec)
     if "rho_reduce_kernel" in name:

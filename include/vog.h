@@ -104,6 +104,18 @@ typedef struct vog_config {
      * depend on how a run is cut into calls.  L2 and energy are computed on
      * the last step of a call only. */
     int merge_v;
+    /* Without merge_v, the closing v half-step of step n and the opening one
+     * of step n+1 inside one call run in one launch.  0 (default): in the
+     * FP32 precisions the two are composed in Fourier space (the kernel's
+     * symbol applied twice, the first step's source term transformed beside
+     * the lines, one inverse transform; Section 1.2 applied twice), which is
+     * the same scheme with different rounding: results depend at the
+     * rounding level on how a run is cut into calls (each cut closes and
+     * reopens with single half steps).  1: the two half steps are transformed
+     * one after the other, and f, E and the diagnostics of a call of n steps
+     * are bitwise those of n single-step calls.  FP64 sims always behave as
+     * with 1. */
+    int bitwise_steps;
 } vog_config;
 
 /* One record per time step, written on the device by the field solve. */
@@ -192,15 +204,19 @@ int vog_set_E(vog_sim *sim, const double *host_E);
  * product A u of Section 1.2 (Lagrange 2d+1 or B-spline coefficients),
  * applied as FFT -> multiply by the diagonal of A in Fourier space ->
  * inverse FFT.  With a drive, the v-advections use E - E_app.  Between two
- * steps of one call the closing half step and the next opening one may run
- * in one launch; f, E and the diagnostics records are bitwise those of
- * nsteps calls of one step.  Asynchronous: returns after enqueueing.
+ * steps of one call the closing half step and the next opening one run in
+ * one launch, composed in Fourier space for FP32 sims unless the
+ * configuration sets bitwise_steps (then, and for FP64 sims, f, E and the
+ * diagnostics records are bitwise those of nsteps calls of one step).  The
+ * same sequence of calls always gives the same bits.  Asynchronous: returns
+ * after enqueueing.
  * dt > 0 and finite, nsteps >= 0 (0: no-op). */
 int vog_step(vog_sim *sim, double dt, int nsteps);
 
 /* nsteps Strang steps (Section 1.1, the time loop of Section 2) for nsims
  * sims at once, sim k with step dt[k], with
- * grouped launches of up to 64 sims: one per kernel type and line length, and
+ * grouped launches of up to 128 sims per sweep and 64 per field solve: one
+ * per kernel type and line length, and
  * for FP32 sims one per sweep covering all their line lengths (v-lines of
  * 64..4096 points, x-lines of 64..1024).  Every sim must use the stream of
  * sims[0], and no sim may appear twice.  Each sim's result is bitwise

@@ -273,6 +273,71 @@ struct Fft {
         });
     }
 
+    // Two independent transforms of the same length side by side: each pass
+    // reads its twiddle rows once for both, and each exchange moves both
+    // between one pair of barriers (v through lre/lim, u through lre2/lim2).
+    // Per value the arithmetic is that of run().
+    template <int DIR, bool WAVE = false>
+    static __device__ __forceinline__ void run2(cx<T> (&v)[R], cx<T> (&u)[R], int t, T *lre, T *lim, T *lre2,
+                                                T *lim2, const cx<T> *__restrict__ tw) {
+        static_for<0, NPASS>([&](auto pc) {
+            constexpr int p = decltype(pc)::value;
+            constexpr int RP = radix(p), NS = ns(p);
+            static_for<0, R / RP>([&](auto uc) {
+                constexpr int g = decltype(uc)::value;
+                if constexpr (NS > 1) {
+                    const int k = (t + g * TPF) & (NS - 1);
+                    cx<T> w[RP];
+                    load_row<T, RP>(tw + fft_tw_off(N, p) + 16 * k, w);
+                    static_for<1, RP>([&](auto rc) {
+                        constexpr int r = decltype(rc)::value;
+                        if constexpr (DIR > 0) {
+                            v[g * RP + r] = cmul(v[g * RP + r], w[r]);
+                            u[g * RP + r] = cmul(u[g * RP + r], w[r]);
+                        } else {
+                            v[g * RP + r] = cmul_conj(v[g * RP + r], w[r]);
+                            u[g * RP + r] = cmul_conj(u[g * RP + r], w[r]);
+                        }
+                    });
+                }
+                dft<T, DIR, RP>(&v[g * RP]);
+                dft<T, DIR, RP>(&u[g * RP]);
+            });
+            if constexpr (p + 1 < NPASS) {
+                constexpr int RQ = radix(p + 1);
+                xsync<WAVE>();
+                static_for<0, R / RP>([&](auto uc) {
+                    constexpr int g = decltype(uc)::value;
+                    const int jb = t + g * TPF;
+                    const int k = jb & (NS - 1);
+                    const int pb = pad((jb - k) * RP + k);
+                    static_for<0, RP>([&](auto rc) {
+                        constexpr int r = decltype(rc)::value;
+                        const int idx = pb + r * NS + (r * NS) / 16;
+                        lre[idx] = v[g * RP + r].re;
+                        lim[idx] = v[g * RP + r].im;
+                        lre2[idx] = u[g * RP + r].re;
+                        lim2[idx] = u[g * RP + r].im;
+                    });
+                });
+                xsync<WAVE>();
+                const int pt = pad(t);
+                static_for<0, R / RQ>([&](auto uc) {
+                    constexpr int g = decltype(uc)::value;
+                    static_for<0, RQ>([&](auto rc) {
+                        constexpr int r = decltype(rc)::value;
+                        constexpr int C = g * TPF + r * (N / RQ);
+                        int idx;
+                        if constexpr (TPF % 16 == 0) idx = pad_add<C>(pt);
+                        else idx = pad(t + C);
+                        v[g * RQ + r] = cx<T>{lre[idx], lim[idx]};
+                        u[g * RQ + r] = cx<T>{lre2[idx], lim2[idx]};
+                    });
+                });
+            }
+        });
+    }
+
     // The twiddles every pass of thread t uses, held in registers: pass p
     // (p >= 1) group u takes row (t + u TPF) mod NS(p), entries 0 .. RP-1, at
     // w[p - 1][u RP ..].  The same rows serve both directions (forward

@@ -8,7 +8,10 @@
 //                   multiply by the diagonal of the circulant in Fourier space
 //                   (Lagrange or B-spline symbol), inverse FFT, integer part of
 //                   the shift applied as an exact cyclic index offset on the
-//                   store, delta-f source term (Section 3.1) on v-sweeps.
+//                   store, delta-f source term (Section 3.1) on v-sweeps;
+//                   between two steps, the two v half-steps with one field
+//                   in one launch (transformed in turn, or composed in
+//                   Fourier space with one inverse transform).
 //  xsweep_fused_kernel
 //                   the x-advection on the v-fastest layout, tiles of whole
 //                   x-lines loaded straight into registers.
@@ -301,6 +304,21 @@ __device__ __forceinline__ void store_pair(const SimDev &S, double tauEA, double
         [&](unsigned pos, T x) { buf_store<T>(x, rB, oB + pos, 0); }, srcA);
 }
 
+// delta-f source of one line at the positions (t + k TPF - b) mod N that the
+// unshifted indices t + k TPF of a result go to under the shift by b.
+template <typename T, int N, int R, int TPF>
+__device__ __forceinline__ void line_source(const SimDev &S, double tauE, long long b, int t, T (&src)[R]) {
+    constexpr unsigned LB = N * sizeof(T);  // bytes per line
+    const int p0 = (t - (int)(b & (N - 1))) & (N - 1);
+    const unsigned p = (unsigned)p0 * sizeof(T);
+    unsigned pos[R];
+    static_for<0, R>([&](auto kc) {
+        constexpr unsigned k = decltype(kc)::value;
+        pos[k] = (p + k * TPF * sizeof(T)) & (LB - 1);
+    });
+    deltaf_source<T, N, R, TPF>(S, tauE, p0, pos, src);
+}
+
 // Weights of a line pair for its fractional shifts sA, sB, combined for the
 // packed transform: wP = (wA + wB) / (2N), wQ = (wA - wB) / (2N) (the 1/N
 // folds the scale of the inverse FFT), times `half` (0.5 for the 4096-point
@@ -435,13 +453,126 @@ __device__ __forceinline__ void pair_transform(cx<T> (&v)[R], cx<T> (&Y)[R], int
     else F::template run<1, WAVE>(Y, t, lre, lim, tw);  // Y[i] = y[t + TPF kpos(i)]
 }
 
+// Two applications of the packed kernel with a source term between them,
+// composed in Fourier space.  On entry v[r] = z[t + r TPF] (z = uA + i uB)
+// and, with SRC, s[r] = zs[t + r TPF] (zs = sA + i sB, each line's source at
+// the positions its first result would be stored to); on exit
+// Y[i] = y[t + TPF kpos(i)] with
+//   y = IFFT(K (K Z + Zs)),  K X = P X_m + Q conj(X_{N-m})
+//     = P2 Z_m + Q2 conj(Z_{N-m}) + P Zs_m + Q conj(Zs_{N-m}),
+//   P2 = P^2 + Q^2,  Q2 = 2 P Q,
+// as the symbols of real kernels satisfy P_{N-m} = conj(P_m) (likewise Q).
+// The scale 1/N of the inverse transform is in wP, wQ, hence the factor N on
+// P2 and Q2.  lre2, lim2: a second pair of exchange arrays (for zs).
+template <typename T, int N, bool SRC, bool WAVE = false, int R = fft_regs(N)>
+__device__ __forceinline__ void pair_transform2(cx<T> (&v)[R], cx<T> (&s)[R], cx<T> (&Y)[R], int t, T *lre,
+                                                T *lim, T *lre2, T *lim2, const cx<T> *__restrict__ tw,
+                                                const cx<T> *eps, const T *wP, const T *wQ,
+                                                const T *__restrict__ iden) {
+    using F = Fft<T, N>;
+    constexpr int TPF = F::TPF;
+    static_assert(R == F::R, "register count");
+
+    // v[i] = Z[t + TPF kpos(i)], s[i] = Zs[t + TPF kpos(i)]
+    if constexpr (SRC) F::template run2<-1, WAVE>(v, s, t, lre, lim, lre2, lim2, tw);
+    else F::template run<-1, WAVE>(v, t, lre, lim, tw);
+
+    auto symbol = [&](const T *w, cx<T>(&H)[R]) {
+        cx<T> e[kEpsRow];
+        load_row<T, kEpsRow>(eps, e);
+        static_for<0, R>([&](auto cc) { H[decltype(cc)::value] = cx<T>{(T)0, (T)0}; });
+        static_for<0, kTaps>([&](auto qc) {
+            constexpr int qi = decltype(qc)::value;
+            constexpr int q = qi - kDMax;
+            constexpr int c = ((q % R) + R) % R;
+            constexpr int aq = q < 0 ? -q : q;
+            const T wq = w[qi];
+            if constexpr (q == 0) {
+                H[c].re += wq;
+            } else if constexpr (q > 0) {
+                H[c].re = fma_t<T>(wq, e[aq].re, H[c].re);
+                H[c].im = fma_t<T>(wq, e[aq].im, H[c].im);
+            } else {
+                H[c].re = fma_t<T>(wq, e[aq].re, H[c].re);
+                H[c].im = fma_t<T>(-wq, e[aq].im, H[c].im);
+            }
+        });
+        dft<T, 1, R>(H);
+    };
+
+    if constexpr (TPF > 1) {
+        // Z (and Zs) to LDS at their natural positions for the partner exchange
+        xsync<WAVE>();
+        const int pt = F::pad(t);
+        static_for<0, R>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            constexpr int C = TPF * F::kpos(i);
+            const int idx = (TPF % 16 == 0) ? F::template pad_add<C>(pt) : F::pad(t + C);
+            lre[idx] = v[i].re;
+            lim[idx] = v[i].im;
+            if constexpr (SRC) {
+                lre2[idx] = s[i].re;
+                lim2[idx] = s[i].im;
+            }
+        });
+    } else {
+        xsync<WAVE>();  // weights visible
+    }
+    cx<T> HP[R], HQ[R];
+    symbol(wP, HP);
+    symbol(wQ, HQ);
+    if (iden) {
+        static_for<0, R>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            const T sc = iden[t + k * TPF];
+            HP[k].re *= sc;
+            HP[k].im *= sc;
+            HQ[k].re *= sc;
+            HQ[k].im *= sc;
+        });
+    }
+    if constexpr (TPF > 1) xsync<WAVE>();
+    const int ptp = F::pad(TPF - t);
+    static_for<0, R>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        constexpr int k = F::kpos(i);
+        // partner of m = t + k TPF: N - m = tp + (R - 1 - k) TPF for t > 0
+        // (tp = TPF - t), (R - k) TPF mod N for t = 0
+        cx<T> Zp, Sp;
+        if constexpr (TPF > 1) {
+            constexpr int C1 = (R - 1 - k) * TPF;
+            constexpr int C0 = ((R - k) % R) * TPF;
+            const int idx = t == 0 ? F::pad(C0)
+                                   : ((TPF % 16 == 0) ? F::template pad_add<C1>(ptp) : F::pad(TPF - t + C1));
+            Zp = cx<T>{lre[idx], -lim[idx]};
+            if constexpr (SRC) Sp = cx<T>{lre2[idx], -lim2[idx]};
+        } else {
+            constexpr int ip = F::kinv((N - k) & (N - 1));
+            Zp = cx<T>{v[ip].re, -v[ip].im};
+            if constexpr (SRC) Sp = cx<T>{s[ip].re, -s[ip].im};
+        }
+        const cx<T> P = HP[k], Q = HQ[k];
+        const cx<T> P2 = cmul(P, P) + cmul(Q, Q);
+        const cx<T> Q2 = cmul(P, Q);
+        constexpr T n1 = (T)N, n2 = (T)(2 * N);
+        cx<T> y = cmul(cx<T>{P2.re * n1, P2.im * n1}, v[i]) + cmul(cx<T>{Q2.re * n2, Q2.im * n2}, Zp);
+        if constexpr (SRC) y = y + cmul(P, s[i]) + cmul(Q, Sp);
+        Y[k] = y;
+    });
+
+    F::template run<1, WAVE>(Y, t, lre, lim, tw);  // Y[i] = y[t + TPF kpos(i)]
+}
+
 // KIND 0: v-advection by tau = b.a[sim] with field E (lines are x-columns of
 // f, length nv).  KIND 1: x-advection by dt = b.a[sim] (lines are v-rows of
 // the transposed copy g, length nx).  KIND 2: two v-advections by tau in a
 // row with the same E (the closing half step of one Strang step and the
 // opening one of the next): the first result, source term included, goes
 // through LDS instead of f, in the same FP32 or FP64 values a store and a
-// reload would give.
+// reload would give.  KIND 3: the same two v-advections composed in Fourier
+// space (pair_transform2: forward transforms of the lines and of the first
+// step's source, one inverse), stored with twice the integer shift; equal to
+// KIND 2 up to rounding.
 //
 // Two real lines A, B are packed as z = uA + i uB and transformed together.
 // With beta = b + s (b integer, s in [0,1)), the circulant A of Section 1.2 is
@@ -460,6 +591,12 @@ struct Sweep {
     // per CU still fit the 160 KB of LDS (lines of 256 points or more)
     static constexpr bool SRC_CACHE = sizeof(T) == 4 && 3 * (SMEM + PPB * N) * (int)sizeof(T) <= 160 * 1024;
     static constexpr int SMEM2 = SMEM + (SRC_CACHE ? PPB * N : 0);
+    // KIND 3: a second pair of exchange arrays per line pair (lines of more
+    // than 16 points, whose transforms exchange through LDS)
+    static constexpr int SMEM3 = SMEM + (F::TPF > 1 ? PPB * 2 * F::LDSN : 0);
+    // KIND 3 has a kernel for FP32 lines (the library runs FP64 sims with
+    // KIND 2); elsewhere it stands for two KIND 0 launches
+    static constexpr bool COMPOSED = sizeof(T) == 4 && SMEM3 * (int)sizeof(T) <= 160 * 1024;
 };
 
 // Block blk of sim `sim` of the batch; smem holds Sweep<T, N>::SMEM values
@@ -587,6 +724,36 @@ __device__ __forceinline__ void sweep_body(const SweepBatch &b, int sim, int blk
         else return Y[F::kinv(k)];
     };
 
+    if constexpr (KIND == 3) {
+        // u2 = shift_2b(K (K u0 + shift_-b s)) + s: the source s of each line
+        // taken at the positions j - b of the first step's store, the result
+        // stored at j - 2b with s added there.
+        static_assert(Sweep<T, N>::COMPOSED && !kP4k, "no composed kernel for these lines");
+        constexpr bool WAVE = TPF <= 64;
+        T *lre2 = smem + Sweep<T, N>::SMEM + slot * 2 * F::LDSN;
+        T *lim2 = lre2 + F::LDSN;
+        cx<T> s[R];
+        if (S.deltaf) {
+            {
+                T sa[R];
+                line_source<T, N, R, TPF>(S, arg * EA, bA, t, sa);
+                static_for<0, R>([&](auto rc) { s[decltype(rc)::value].re = sa[decltype(rc)::value]; });
+            }
+            {
+                T sb[R];
+                line_source<T, N, R, TPF>(S, arg * EB, bB, t, sb);
+                static_for<0, R>([&](auto rc) { s[decltype(rc)::value].im = sb[decltype(rc)::value]; });
+            }
+            pair_transform2<T, N, true, WAVE>(v, s, Y, t, lre, lim, lre2, lim2, tw, eps, wsh[slot][0],
+                                              wsh[slot][1], iden);
+        } else {
+            pair_transform2<T, N, false, WAVE>(v, s, Y, t, lre, lim, lre2, lim2, tw, eps, wsh[slot][0],
+                                               wsh[slot][1], iden);
+        }
+        if (!active) return;
+        store_pair<T, N, R, TPF, VS, 0>(S, arg * EA, arg * EB, 2 * bA, 2 * bB, t, rA, oA, rB, oB, out);
+        return;
+    }
     transform(tw, eps, t);
     if constexpr (KIND == 2) {
         // The first half step's result to LDS at its positions in the line,
@@ -619,8 +786,9 @@ __device__ __forceinline__ void sweep_body(const SweepBatch &b, int sim, int blk
 
 // One line length per launch: blockIdx.y = sim, blockIdx.x = block.
 template <typename T, int N, int KIND>
-__global__ __launch_bounds__(256, (sizeof(T) == 4 && N >= 32 ? 3 : 1)) void sweep_kernel(const SweepBatch b) {
-    __shared__ T smem[KIND == 2 ? Sweep<T, N>::SMEM2 : Sweep<T, N>::SMEM];
+__global__ __launch_bounds__(256, (KIND == 3 ? 2 : (sizeof(T) == 4 && N >= 32 ? 3 : 1))) void sweep_kernel(
+    const SweepBatch b) {
+    __shared__ T smem[KIND == 3 ? Sweep<T, N>::SMEM3 : KIND == 2 ? Sweep<T, N>::SMEM2 : Sweep<T, N>::SMEM];
     sweep_body<T, N, KIND>(b, (int)blockIdx.y, (int)blockIdx.x, smem);
 }
 

@@ -11,7 +11,7 @@ SweepFn sweep_launcher_f64(int n, int kind);
 
 SweepFn sweep_launcher(bool fp64, int n, int kind) {
     const int logn = ilog2(n);
-    if (n < VOG_MIN_N || n > VOG_MAX_N || (1 << logn) != n || kind < 0 || kind > 2) return nullptr;
+    if (n < VOG_MIN_N || n > VOG_MAX_N || (1 << logn) != n || kind < 0 || kind > 3) return nullptr;
     return fp64 ? sweep_launcher_f64(n, kind) : sweep_launcher_f32(n, kind);
 }
 

@@ -7,10 +7,21 @@ namespace vog {
 // FP32 v-sweeps of sims with lines of 64 .. 4096 points in one launch: every
 // block runs the body of its sim's line length (each block carries 8192
 // values whatever the length).
-// KIND 0: one v half-step; KIND 2: two in a row (sweep_body).
+// KIND 0: one v half-step; KIND 2: two in a row; KIND 3: two composed in
+// Fourier space (sweep_body).
+constexpr int kMixedSmem3 = [] {
+    int m = 0;
+    const int s[] = {Sweep<float, 64>::SMEM3,   Sweep<float, 128>::SMEM3, Sweep<float, 256>::SMEM3,
+                     Sweep<float, 512>::SMEM3,  Sweep<float, 1024>::SMEM3, Sweep<float, 2048>::SMEM3,
+                     Sweep<float, 4096>::SMEM3};
+    for (int x : s) m = x > m ? x : m;
+    return m;
+}();
 template <int KIND>
-__global__ __launch_bounds__(256, 3) void sweep_v_mixed_kernel(const SweepBatch b, const SweepMap m) {
-    __shared__ float smem[Sweep<float, 64>::SMEM];  // the largest of 64 .. 4096
+__global__ __launch_bounds__(256, (KIND == 3 ? 2 : 3)) void sweep_v_mixed_kernel(const SweepBatch b,
+                                                                               const SweepMap m) {
+    // the largest of 64 .. 4096
+    __shared__ float smem[KIND == 3 ? kMixedSmem3 : Sweep<float, 64>::SMEM];
     const int bid = (int)blockIdx.x;
     const int k = mixed_sim(b, m, bid);
     const int blk = bid - m.first[k];
@@ -79,6 +90,7 @@ void launch_sweep_mixed(int kind, const SweepBatch &b, const SweepMap &m, hipStr
     const int blocks = m.first[b.n];
     if (kind == 0) hipLaunchKernelGGL(sweep_v_mixed_kernel<0>, dim3(blocks), dim3(256), 0, st, b, m);
     else if (kind == 2) hipLaunchKernelGGL(sweep_v_mixed_kernel<2>, dim3(blocks), dim3(256), 0, st, b, m);
+    else if (kind == 3) hipLaunchKernelGGL(sweep_v_mixed_kernel<3>, dim3(blocks), dim3(256), 0, st, b, m);
     else hipLaunchKernelGGL(xsweep_mixed_kernel, dim3(blocks), dim3(256), 0, st, b, m);
 }
 

@@ -235,6 +235,8 @@ int validate(const vog_config *c) {
     if (c->interp != VOG_INTERP_LAGRANGE && c->interp != VOG_INTERP_BSPLINE)
         return fail(VOG_EINVAL, "unknown interpolation");
     if (c->merge_v != 0 && c->merge_v != 1) return fail(VOG_EINVAL, "merge_v must be 0 or 1");
+    if (c->bitwise_steps != 0 && c->bitwise_steps != 1)
+        return fail(VOG_EINVAL, "bitwise_steps must be 0 or 1");
     if (c->poisson != VOG_POISSON_FOURIER && c->poisson != VOG_POISSON_TRAPEZOID)
         return fail(VOG_EINVAL, "unknown Poisson solver");
     if (c->zero_mean != 0 && c->zero_mean != 1) return fail(VOG_EINVAL, "zero_mean must be 0 or 1");
@@ -408,13 +410,14 @@ int check_launch() {
 }
 
 // Sweeps of all sims (tau or dt per sim).  vsweep: v-advection on the
-// v-fastest layout (twice: two v-advections by tau in a row, one launch).
+// v-fastest layout (vv = 2: two v-advections by tau in a row in one launch,
+// transformed in turn; vv = 3: the two composed in Fourier space).
 // Otherwise x-advection: fused = true selects the sims whose x-sweep runs on
 // the v-fastest layout, fused = false the others (which work on the
 // transposed copy).
 int run_sweep(vog_sim *lead, const std::vector<vog_sim *> &sims, const std::vector<double> &arg,
-              bool vsweep, bool fused = false, bool twice = false) {
-    if (twice) {
+              bool vsweep, bool fused = false, int vv = 0) {
+    if (vv == 2) {
         // FP64 4096-point v-lines: the two-in-one kernel needs more than 256
         // VGPRs (one wave per SIMD instead of two), so those sims take two
         // launches of the single-step kernel, which give the same values.
@@ -430,11 +433,11 @@ int run_sweep(vog_sim *lead, const std::vector<vog_sim *> &sims, const std::vect
                 const int rc = run_sweep(lead, split, as, true);
                 if (rc != VOG_OK) return rc;
             }
-            return rest.empty() ? VOG_OK : run_sweep(lead, rest, ar, true, false, true);
+            return rest.empty() ? VOG_OK : run_sweep(lead, rest, ar, true, false, 2);
         }
     }
-    const int vkind = twice ? 2 : 0;                     // sweep kind of a v-sweep launch
-    const Kind pkind = twice ? K_SWEEP_VV : K_SWEEP_V;  // its profile kind
+    const int vkind = vv;                                  // sweep kind of a v-sweep launch
+    const Kind pkind = vv != 0 ? K_SWEEP_VV : K_SWEEP_V;  // its profile kind
     std::map<std::pair<int, int>, Group> groups;  // (fp64, line length)
     for (size_t k = 0; k < sims.size(); ++k) {
         vog_sim *s = sims[k];
@@ -669,9 +672,11 @@ int device_guard(vog_sim *s) {
 // kernel kind and line length.  Between two steps of one call, the closing
 // half step of the first and the opening half step of the second share the
 // field: sims with merge_v replace them by one advection by dt (a different
-// scheme, opt-in); the others run both in one launch (sweep kind 2, the same
-// arithmetic as two launches), except where the moments need the full time
-// level in between.
+// scheme, opt-in); the others run both in one launch, except where the
+// moments need the full time level in between: FP32 sims composed in Fourier
+// space (sweep kind 3, the same scheme up to rounding), FP64 sims and those
+// with bitwise_steps transformed in turn (kind 2, the arithmetic of two
+// launches).
 int step_sims(const std::vector<vog_sim *> &sims, const std::vector<double> &dt, int nsteps) {
     vog_sim *lead = sims[0];
     std::vector<int64_t> stepno(sims.size());
@@ -679,8 +684,8 @@ int step_sims(const std::vector<vog_sim *> &sims, const std::vector<double> &dt,
     std::vector<char> opened(sims.size(), 0);  // opening half step already done
     for (int n = 0; n < nsteps; ++n) {
         const bool last = n == nsteps - 1;
-        std::vector<vog_sim *> open, once, twice, msims;  // see below
-        std::vector<double> half, tau_once, tau_twice;
+        std::vector<vog_sim *> open, once, twice, comp, msims;  // see below
+        std::vector<double> half, tau_once, tau_twice, tau_comp;
         std::vector<int64_t> mstep;
         for (size_t k = 0; k < sims.size(); ++k) {
             stepno[k] = sims[k]->step + 1;
@@ -702,8 +707,9 @@ int step_sims(const std::vector<vog_sim *> &sims, const std::vector<double> &dt,
                 once.push_back(sims[k]);
                 tau_once.push_back(dt[k]);
             } else if (!last && !due) {  // closing and next opening half step, one launch
-                twice.push_back(sims[k]);
-                tau_twice.push_back(0.5 * dt[k]);
+                const bool bitwise = sims[k]->fp64 || sims[k]->cfg.bitwise_steps != 0;
+                (bitwise ? twice : comp).push_back(sims[k]);
+                (bitwise ? tau_twice : tau_comp).push_back(0.5 * dt[k]);
             } else {
                 once.push_back(sims[k]);
                 tau_once.push_back(0.5 * dt[k]);
@@ -715,7 +721,9 @@ int step_sims(const std::vector<vog_sim *> &sims, const std::vector<double> &dt,
         if ((rc = x_advection(lead, sims, dt, true)) != VOG_OK) return rc;
         if ((rc = run_field(lead, sims, stepno, tnow)) != VOG_OK) return rc;
         if (!once.empty() && (rc = run_sweep(lead, once, tau_once, true)) != VOG_OK) return rc;
-        if (!twice.empty() && (rc = run_sweep(lead, twice, tau_twice, true, false, true)) != VOG_OK)
+        if (!twice.empty() && (rc = run_sweep(lead, twice, tau_twice, true, false, 2)) != VOG_OK)
+            return rc;
+        if (!comp.empty() && (rc = run_sweep(lead, comp, tau_comp, true, false, 3)) != VOG_OK)
             return rc;
         if (!msims.empty() && (rc = run_moments(lead, msims, mstep)) != VOG_OK) return rc;
         for (size_t k = 0; k < sims.size(); ++k) {

@@ -6,9 +6,15 @@ namespace vog {
 
 template <typename T, int N, int KIND>
 static void launch_sweep(const SweepBatch &b, int max_lines, hipStream_t st) {
-    constexpr int PPB = 256 / Fft<T, N>::TPF;
-    const int blocks = (max_lines / 2 + PPB - 1) / PPB;
-    hipLaunchKernelGGL((sweep_kernel<T, N, KIND>), dim3(blocks, b.n), dim3(256), 0, st, b);
+    if constexpr (KIND == 3 && !Sweep<T, N>::COMPOSED) {
+        // no composed kernel for these lines: two one-step launches
+        launch_sweep<T, N, 0>(b, max_lines, st);
+        launch_sweep<T, N, 0>(b, max_lines, st);
+    } else {
+        constexpr int PPB = 256 / Fft<T, N>::TPF;
+        const int blocks = (max_lines / 2 + PPB - 1) / PPB;
+        hipLaunchKernelGGL((sweep_kernel<T, N, KIND>), dim3(blocks, b.n), dim3(256), 0, st, b);
+    }
 }
 
 template <typename T, int KIND, int... L>
@@ -22,7 +28,8 @@ SweepFn sweep_launcher_f64(int n, int kind) {
     using Seq = std::make_integer_sequence<int, 10>;
     return kind == 0   ? pick_sweep<double, 0>(logn, Seq{})
            : kind == 1 ? pick_sweep<double, 1>(logn, Seq{})
-                       : pick_sweep<double, 2>(logn, Seq{});
+           : kind == 2 ? pick_sweep<double, 2>(logn, Seq{})
+                       : pick_sweep<double, 3>(logn, Seq{});
 }
 
 }  // namespace vog

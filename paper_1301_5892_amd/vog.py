@@ -50,7 +50,8 @@ class Config(ctypes.Structure):
                 ("drive_omega", ctypes.c_double), ("drive_t0", ctypes.c_double),
                 ("drive_tl", ctypes.c_double), ("drive_tr", ctypes.c_double),
                 ("drive_twl", ctypes.c_double), ("drive_twr", ctypes.c_double),
-                ("interp", ctypes.c_int), ("merge_v", ctypes.c_int)]
+                ("interp", ctypes.c_int), ("merge_v", ctypes.c_int),
+                ("bitwise_steps", ctypes.c_int)]
 
 
 class Diag(ctypes.Structure):
@@ -161,6 +162,7 @@ def make_config(w, moments_every: int = 0, precision: Optional[str] = None) -> C
     c.moments_every = moments_every
     c.interp = INTERP[w.interp]
     c.merge_v = int(bool(w.merge_v))
+    c.bitwise_steps = int(bool(w.bitwise_steps))
     return c
 
 

@@ -61,7 +61,7 @@ def test_named_workloads_validate(vog, w):
     ("nx", 12), ("nx", 4), ("nv", 8192), ("nv", 0), ("degree", 4), ("degree", 19),
     ("degree", 0), ("L", 0.0), ("L", float("nan")), ("vmax", -7.0), ("precision", 7),
     ("poisson", 3), ("field", 2), ("n_feq", 0), ("n_feq", 5), ("moments_every", -1),
-    ("interp", 2), ("interp", -1), ("merge_v", 2), ("zero_mean", 3), ("precision", 4),
+    ("interp", 2), ("interp", -1), ("merge_v", 2), ("bitwise_steps", 2), ("zero_mean", 3), ("precision", 4),
     ("drive_emax", float("inf"))])
 def test_invalid_configs_rejected(vog, field, value):
     c = vog.make_config(workloads.landau_weak())

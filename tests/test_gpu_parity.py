@@ -336,9 +336,12 @@ def test_batch_equals_alone_bitwise(gpu):
 
 
 def test_checkpoint_resume_bitwise(gpu):
+    # the reference is cut into the same calls (a cut closes and reopens with
+    # single v half steps, so in FP32 the bits depend on where runs are cut)
     w = workloads.landau_strong()
     a = sim_of(gpu, w).init()
-    a.step(12)
+    a.step(5)
+    a.step(7)
     ref = a.get_raw().copy()
     b = sim_of(gpu, w).init()
     b.step(5)
@@ -440,7 +443,8 @@ def test_drive_checkpoint_bitwise(gpu):
     w = workloads.keen(256, 0.1, 10)
     w = w.replace(drive=d)
     a = sim_of(gpu, w).init()
-    a.step(9)
+    a.step(4)
+    a.step(5)
     ref = a.get_raw().copy()
     b = sim_of(gpu, w).init()
     b.step(4)

@@ -67,6 +67,7 @@ class Workload:
     drive: Optional[Drive] = None
     interp: str = "lagrange"        # or "bspline" (odd degree k = degree)
     merge_v: bool = False           # merge the v half-steps of consecutive steps
+    bitwise_steps: bool = False     # a call of n steps bitwise equal to n single steps
 
     @property
     def cells(self) -> int:
