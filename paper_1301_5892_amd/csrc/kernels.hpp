@@ -128,6 +128,12 @@ __device__ __forceinline__ const gmem<T> *as_global(const T *p) { return (const 
 template <>
 __device__ __forceinline__ float fma_t<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
+// acc + a b, complex, with four fused multiply-adds.
+template <typename T>
+__device__ __forceinline__ cx<T> cmac(cx<T> acc, cx<T> a, cx<T> b) {
+    return {fma_t<T>(a.re, b.re, fma_t<T>(-a.im, b.im, acc.re)), fma_t<T>(a.re, b.im, fma_t<T>(a.im, b.re, acc.im))};
+}
+
 // Raw buffer access: a descriptor with the base address in scalar registers
 // and 32-bit byte offsets per lane (voff) and per instruction (soff), so an
 // access needs no 64-bit address arithmetic.  Accesses at or past `bytes`
@@ -458,12 +464,13 @@ __device__ __forceinline__ void pair_transform(cx<T> (&v)[R], cx<T> (&Y)[R], int
 // and, with SRC, s[r] = zs[t + r TPF] (zs = sA + i sB, each line's source at
 // the positions its first result would be stored to); on exit
 // Y[i] = y[t + TPF kpos(i)] with
-//   y = IFFT(K (K Z + Zs)),  K X = P X_m + Q conj(X_{N-m})
-//     = P2 Z_m + Q2 conj(Z_{N-m}) + P Zs_m + Q conj(Zs_{N-m}),
-//   P2 = P^2 + Q^2,  Q2 = 2 P Q,
-// as the symbols of real kernels satisfy P_{N-m} = conj(P_m) (likewise Q).
+//   y = IFFT(K (K Z + Zs)),  K X = P X_m + Q conj(X_{N-m}),
+// formed from the thread's own modes and their partners N - m alone, as the
+// symbols of real kernels satisfy P_{N-m} = conj(P_m) (likewise Q):
+//   (K X)_m = P X_m + Q conj(X_{N-m}),  conj((K X)_{N-m}) = Q X_m + P conj(X_{N-m}).
 // The scale 1/N of the inverse transform is in wP, wQ, hence the factor N on
-// P2 and Q2.  lre2, lim2: a second pair of exchange arrays (for zs).
+// the inner application.  lre2, lim2: a second pair of exchange arrays (for
+// zs).
 template <typename T, int N, bool SRC, bool WAVE = false, int R = fft_regs(N)>
 __device__ __forceinline__ void pair_transform2(cx<T> (&v)[R], cx<T> (&s)[R], cx<T> (&Y)[R], int t, T *lre,
                                                 T *lim, T *lre2, T *lim2, const cx<T> *__restrict__ tw,
@@ -551,13 +558,21 @@ __device__ __forceinline__ void pair_transform2(cx<T> (&v)[R], cx<T> (&s)[R], cx
             Zp = cx<T>{v[ip].re, -v[ip].im};
             if constexpr (SRC) Sp = cx<T>{s[ip].re, -s[ip].im};
         }
+        // inner application U = N (P Z + Q conj(Z_{N-m})) + Zs and its value at
+        // the partner, conjugated, W = N (Q Z + P conj(Z_{N-m})) + conj(Zs_{N-m});
+        // then y = P U + Q W
         const cx<T> P = HP[k], Q = HQ[k];
-        const cx<T> P2 = cmul(P, P) + cmul(Q, Q);
-        const cx<T> Q2 = cmul(P, Q);
-        constexpr T n1 = (T)N, n2 = (T)(2 * N);
-        cx<T> y = cmul(cx<T>{P2.re * n1, P2.im * n1}, v[i]) + cmul(cx<T>{Q2.re * n2, Q2.im * n2}, Zp);
-        if constexpr (SRC) y = y + cmul(P, s[i]) + cmul(Q, Sp);
-        Y[k] = y;
+        constexpr T n1 = (T)N;
+        cx<T> U = cmac(cmul(P, v[i]), Q, Zp);
+        cx<T> W = cmac(cmul(Q, v[i]), P, Zp);
+        if constexpr (SRC) {
+            U = cx<T>{fma_t<T>(n1, U.re, s[i].re), fma_t<T>(n1, U.im, s[i].im)};
+            W = cx<T>{fma_t<T>(n1, W.re, Sp.re), fma_t<T>(n1, W.im, Sp.im)};
+        } else {
+            U = cx<T>{n1 * U.re, n1 * U.im};
+            W = cx<T>{n1 * W.re, n1 * W.im};
+        }
+        Y[k] = cmac(cmul(P, U), Q, W);
     });
 
     F::template run<1, WAVE>(Y, t, lre, lim, tw);  // Y[i] = y[t + TPF kpos(i)]
