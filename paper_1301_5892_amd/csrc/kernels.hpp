@@ -343,6 +343,35 @@ __device__ __forceinline__ void pair_weights(int d, int interp, double sA, doubl
     }
 }
 
+// Symbol of the kernel with weights w for the modes m = t + k TPF of one
+// thread (k = 0..R-1): S_m = DFT_R^+ (H)[k] with the tap partial sums
+// H_c = sum_{q = c mod R} w_q exp(2 pi i t q / N), the phases taken from the
+// thread's row of the table eps (exp(2 pi i t q / N), q = 0..kEpsRow-1; the
+// negative taps use their conjugates).
+template <typename T, int R>
+__device__ __forceinline__ void pair_symbol(const cx<T> *eps, const T *w, cx<T> (&H)[R]) {
+    cx<T> e[kEpsRow];
+    load_row<T, kEpsRow>(eps, e);
+    static_for<0, R>([&](auto cc) { H[decltype(cc)::value] = cx<T>{(T)0, (T)0}; });
+    static_for<0, kTaps>([&](auto qc) {
+        constexpr int qi = decltype(qc)::value;
+        constexpr int q = qi - kDMax;
+        constexpr int c = ((q % R) + R) % R;
+        constexpr int aq = q < 0 ? -q : q;
+        const T wq = w[qi];
+        if constexpr (q == 0) {
+            H[c].re += wq;
+        } else if constexpr (q > 0) {
+            H[c].re = fma_t<T>(wq, e[aq].re, H[c].re);
+            H[c].im = fma_t<T>(wq, e[aq].im, H[c].im);
+        } else {
+            H[c].re = fma_t<T>(wq, e[aq].re, H[c].re);
+            H[c].im = fma_t<T>(-wq, e[aq].im, H[c].im);
+        }
+    });
+    dft<T, 1, R>(H);
+}
+
 // The packed product of one line pair: on entry v[r] = z[t + r TPF] with
 // z = uA + i uB; on exit Y[i] = y[t + TPF kpos(i)], y = IFFT(P Z + Q conj(Z_{N-m}))
 // = (kernel A applied to uA) + i (kernel B applied to uB), unshifted.
@@ -366,28 +395,7 @@ __device__ __forceinline__ void pair_transform(cx<T> (&v)[R], cx<T> (&Y)[R], int
 
     F::template run<-1, WAVE>(v, t, lre, lim, tw);  // v[i] = Z[t + TPF kpos(i)]
 
-    auto symbol = [&](const T *w, cx<T>(&H)[R]) {
-        cx<T> e[kEpsRow];
-        load_row<T, kEpsRow>(eps, e);
-        static_for<0, R>([&](auto cc) { H[decltype(cc)::value] = cx<T>{(T)0, (T)0}; });
-        static_for<0, kTaps>([&](auto qc) {
-            constexpr int qi = decltype(qc)::value;
-            constexpr int q = qi - kDMax;
-            constexpr int c = ((q % R) + R) % R;
-            constexpr int aq = q < 0 ? -q : q;
-            const T wq = w[qi];
-            if constexpr (q == 0) {
-                H[c].re += wq;
-            } else if constexpr (q > 0) {
-                H[c].re = fma_t<T>(wq, e[aq].re, H[c].re);
-                H[c].im = fma_t<T>(wq, e[aq].im, H[c].im);
-            } else {
-                H[c].re = fma_t<T>(wq, e[aq].re, H[c].re);
-                H[c].im = fma_t<T>(-wq, e[aq].im, H[c].im);
-            }
-        });
-        dft<T, 1, R>(H);
-    };
+    auto symbol = [&](const T *w, cx<T>(&H)[R]) { pair_symbol<T, R>(eps, w, H); };
 
     if constexpr (TPF > 1) {
         // Z to LDS at its natural position for the partner exchange.
@@ -484,28 +492,7 @@ __device__ __forceinline__ void pair_transform2(cx<T> (&v)[R], cx<T> (&s)[R], cx
     if constexpr (SRC) F::template run2<-1, WAVE>(v, s, t, lre, lim, lre2, lim2, tw);
     else F::template run<-1, WAVE>(v, t, lre, lim, tw);
 
-    auto symbol = [&](const T *w, cx<T>(&H)[R]) {
-        cx<T> e[kEpsRow];
-        load_row<T, kEpsRow>(eps, e);
-        static_for<0, R>([&](auto cc) { H[decltype(cc)::value] = cx<T>{(T)0, (T)0}; });
-        static_for<0, kTaps>([&](auto qc) {
-            constexpr int qi = decltype(qc)::value;
-            constexpr int q = qi - kDMax;
-            constexpr int c = ((q % R) + R) % R;
-            constexpr int aq = q < 0 ? -q : q;
-            const T wq = w[qi];
-            if constexpr (q == 0) {
-                H[c].re += wq;
-            } else if constexpr (q > 0) {
-                H[c].re = fma_t<T>(wq, e[aq].re, H[c].re);
-                H[c].im = fma_t<T>(wq, e[aq].im, H[c].im);
-            } else {
-                H[c].re = fma_t<T>(wq, e[aq].re, H[c].re);
-                H[c].im = fma_t<T>(-wq, e[aq].im, H[c].im);
-            }
-        });
-        dft<T, 1, R>(H);
-    };
+    auto symbol = [&](const T *w, cx<T>(&H)[R]) { pair_symbol<T, R>(eps, w, H); };
 
     if constexpr (TPF > 1) {
         // Z (and Zs) to LDS at their natural positions for the partner exchange
