@@ -1306,7 +1306,8 @@ int vog_profile_read(vog_sim *s, double *ms, int64_t *launches, int nkinds) {
 
 const char *vog_build_info(void) {
     return "libvog gfx950: radix-16 Stockham LDS FFT, paired real lines, integer-shift store, "
-           "x-sweep on the v-fastest layout (XCD-ordered line tiles), rho row sums";
+           "x-sweep on the v-fastest layout (XCD-ordered line tiles), rho row sums, "
+           "v half-steps between steps composed in Fourier space (FP32)";
 }
 
 }  // extern "C"
