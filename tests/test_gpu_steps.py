@@ -137,7 +137,9 @@ def _close(a, b, tol=TOL32):
 
 
 COMPOSED = [
+    ("fp32_deltaf", 64, 8, 7),     # one thread per pair, radix-8 transform
     ("fp32_deltaf", 64, 16, 9),    # one thread per pair (no LDS exchange)
+    ("fp32_plain", 64, 32, 17),    # two threads per pair, one exchange
     ("fp32_deltaf", 64, 64, 17),   # 8 line pairs per block
     ("fp32_deltaf", 32, 1024, 17), # one wave per pair
     ("fp32_deltaf", 32, 2048, 17), # two pairs per block
