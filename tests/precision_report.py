@@ -2,7 +2,7 @@
 
 Runs on a machine with the GPU:
 
-    python tests/precision_report.py --out gpurun_out/precision_report.md
+    python tests/precision_report.py --out REPORT.md
 
 and writes a Markdown section with
   * the strong-Landau case (256 x 512, dt = 0.05, 1000 steps): the drift of
@@ -17,9 +17,10 @@ and writes a Markdown section with
     oracle every 25 steps up to step 300 (the oracle is stepped that far),
     beside the oracle-vs-oracle divergence from f0 rounded to FP32.
 
-    python tests/precision_report.py --splice gpurun_out/precision_report.md
+    python tests/precision_report.py --splice REPORT.md --into DOC.md
 
-puts that section into the design doc between its precision-report markers.
+puts that section into the Markdown file DOC.md between its precision-report
+markers.
 Only the oracle and the C ABI of libvog are used.
 """
 from __future__ import annotations
@@ -183,24 +184,28 @@ def bump_on_tail(lines):
                          "oracle, f0 in FP32: E"], curve))
 
 
-def splice(src, design):
+def splice(src, doc):
     with open(src) as fh:
         body = fh.read().strip()
-    with open(design) as fh:
+    with open(doc) as fh:
         text = fh.read()
     a, b = text.index(BEGIN) + len(BEGIN), text.index(END)
-    with open(design, "w") as fh:
+    with open(doc, "w") as fh:
         fh.write(text[:a] + "\n" + body + "\n" + text[b:])
 
 
 def main():
     p = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    p.add_argument("--out", default=os.path.join(ROOT, "gpurun_out", "precision_report.md"))
+    p.add_argument("--out", default="precision_report.md")
     p.add_argument("--splice", metavar="FILE", default=None,
-                   help="put FILE (a report written with --out) into DESIGN.md")
+                   help="put FILE (a report written with --out) into the file given by --into")
+    p.add_argument("--into", metavar="DOC", default=None,
+                   help="Markdown file with the precision-report markers (with --splice)")
     a = p.parse_args()
     if a.splice:
-        splice(a.splice, os.path.join(ROOT, "DESIGN.md"))
+        if not a.into:
+            p.error("--splice needs --into")
+        splice(a.splice, a.into)
         return
     import torch
     assert torch.cuda.is_available(), "the report runs the GPU path"
@@ -211,7 +216,7 @@ def main():
     print("strong Landau done", flush=True)
     bump_on_tail(lines)
     print("bump-on-tail done", flush=True)
-    os.makedirs(os.path.dirname(a.out), exist_ok=True)
+    os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
     with open(a.out, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print(f"wrote {a.out}")
